@@ -1,0 +1,268 @@
+"""Benchmark: vertex-patch multigrid on one MI355X.
+
+Workload: 3D Poisson, Q4 elements on 64^3 cells of the unit cube (257^3 =
+16,974,593 nodes), right-hand side a seeded sum of 16 Fourier sine modes with
+amplitudes decaying as |kappa|^-2 (seed 1).
+
+A step is one full mixed-precision solve: CG in FP64 preconditioned by one FP32
+V-cycle (multiplicative vertex-patch smoother, matrix-free operator, transfers,
+FP64 coarse solve) until ||r|| <= 1e-8 ||b||, from b resident in HBM to x in
+HBM.  value = nodes x steps / timed seconds.  Outside the timed region the
+script also measures the FP64 solve, one smoothing step and one V-cycle in each
+precision, the colour-pass kernel for the roofline, a short serving run
+(continuous batching, p50/p99 latency) and the CPU oracle on a bounded sample.
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+D, K, L = 3, 4, 6
+RTOL = 1e-8
+PEAK_FP32 = 157.3e12  # MI355X published FP32 vector peak
+PEAK_FP64 = 78.6e12
+
+
+def colour_pass_flops(d, k):
+    """Algorithmic flops of one patch (interior-row residual with reuse + FD solve + update)."""
+    n, m = 2 * k + 1, 2 * k - 1
+    if d == 3:
+        macs = 2 * n ** 3 * m + 3 * n ** 2 * m ** 2 + 2 * n * m ** 3 + 6 * m ** 4
+    else:
+        macs = 2 * n ** 2 * m + 2 * n * m ** 2 + 4 * m ** 3
+    return 2 * macs + 3 * m ** d
+
+
+def colour_pass_bytes(d, k, es):
+    """Algorithmic HBM bytes of one patch: read x closure + b interior, write x interior."""
+    n, m = 2 * k + 1, 2 * k - 1
+    return es * (n ** d + 2 * m ** d)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--serve", type=int, default=120, help="requests in the serving run (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
+    return ap.parse_args()
+
+
+def event_time(fn, stream, reps):
+    import torch
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    e.record(stream)
+    e.synchronize()
+    return s.elapsed_time(e) / reps / 1e3
+
+
+def serving_run(v, n_requests, max_active=16, budget=64 << 30):
+    """Continuous-batching server over a seeded stream of mixed (d, k, level) requests.
+
+    Right-hand sides are assembled on the device before the clock starts.  First
+    a closed-loop run (every request present at t = 0) measures capacity; then
+    the same requests arrive as a Poisson process at 80 % of that capacity and
+    latency (arrival -> completion) is recorded per request.
+    """
+    import synth
+    trace = synth.serving_trace(seed=3, n_requests=n_requests, rate_per_s=1.0)
+    makers = {}
+    for r in trace:
+        key = (r["d"], r["k"], r["level"])
+        if key not in makers:
+            makers[key] = v.Problem(r["d"], r["k"], r["level"], v.VPS_FLAG_FP32_HIERARCHY | v.VPS_FLAG_NO_SOLVER)
+        P = makers[key]
+        r["b"] = P.rhs_sine_modes(r["kappas"], r["coefs"])
+        r["x"] = P.new()
+        r["n"] = P.n()
+    for P in makers.values():
+        P.close()
+    import torch
+    torch.cuda.synchronize()
+
+    def run(scale):
+        srv = v.vps_server_create(budget, max_active)
+        t0 = time.perf_counter()
+        pending = list(trace)
+        arrive, done = {}, {}
+        try:
+            while True:
+                now = time.perf_counter() - t0
+                while pending and pending[0]["arrival"] * scale <= now:
+                    r = pending.pop(0)
+                    t = v.vps_server_submit(srv, r["d"], r["k"], r["level"], r["b"].data_ptr(), r["x"].data_ptr(),
+                                            RTOL, v.VPS_SOLVE_MIXED, 50)
+                    arrive[t] = r["arrival"] * scale
+                active, queued = v.vps_server_step(srv)
+                now = time.perf_counter() - t0
+                for t in arrive:
+                    if t not in done and v.vps_server_poll(srv, t)[0]:
+                        done[t] = now
+                if not pending and len(done) == len(trace):
+                    break
+                if active == 0 and queued == 0 and pending:
+                    time.sleep(max(0.0, pending[0]["arrival"] * scale - (time.perf_counter() - t0)))
+            span = time.perf_counter() - t0
+        finally:
+            v.vps_server_destroy(srv)
+        return span, sorted(done[t] - arrive[t] for t in done)
+
+    total = sum(r["n"] for r in trace)
+    span0, lat0 = run(0.0)
+    capacity = len(trace) / span0
+    rate = 0.8 * capacity
+    span1, lat1 = run(1.0 / rate)
+    q = lambda a, p: a[min(len(a) - 1, int(round(p * (len(a) - 1))))]
+    return {"requests": len(trace), "total_dofs": total, "closed_loop_req_per_s": capacity,
+            "closed_loop_dof_per_s": total / span0, "closed_loop_p50_ms": 1e3 * q(lat0, 0.5),
+            "closed_loop_p99_ms": 1e3 * q(lat0, 0.99), "arrival_rate_per_s": rate,
+            "p50_ms": 1e3 * q(lat1, 0.5), "p99_ms": 1e3 * q(lat1, 0.99), "mean_ms": 1e3 * sum(lat1) / len(lat1),
+            "dof_per_s": total / span1, "max_active": max_active}
+
+
+def cpu_baseline(N, vcycles_per_solve):
+    """The FP64 oracle (NumPy/SciPy) on a bounded sample of the same workload.
+
+    Sample: one multiplicative smoothing step (8 colour passes: global residual
+    + dense-LU patch solves) on the 64^3 Q4 level.  A solve performs two such
+    steps per V-cycle on that level; coarser levels, transfers and the CG
+    vector work are not counted, so the scaled figure is an upper bound for the
+    oracle's solve throughput.
+    """
+    import numpy as np
+    import synth
+    from oracle import mesh, rhs, smoother
+    kap, co = synth.fourier_modes(D, seed=1)
+    b = rhs.rhs_sine_modes(D, K, L, kap, co)
+    x = np.zeros_like(b)
+    # oracle set-up (patch factorisation, index maps, 1D matrices) before the clock
+    mesh.global_1d_matrices(K, L)
+    mesh.boundary_mask(D, K, L)
+    smoother._patch_lu(D, K, L)
+    for c in range(2 ** D):
+        smoother._colour_index_arrays(D, K, L, c)
+    t0 = time.perf_counter()
+    smoother.multiplicative(D, K, L, b, x)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps = 2 * vcycles_per_solve
+    return {"value": N / (t * steps), "unit": "DoF/s", "cores": threads, "kind": "oracle",
+            "sample": "one FP64 oracle smoothing step on 3D Q4 64^3 (%.1f s), scaled to the %d finest-level "
+                      "smoothing steps of one solve (upper bound: coarser levels and CG work not counted)"
+                      % (t, steps),
+            "smoothing_step_s": t}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2405_19004_amd as v
+    import synth
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    P = v.Problem(D, K, L, v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY)
+    N = P.n()
+    kap, co = synth.fourier_modes(D, seed=1)
+    b = P.rhs_sine_modes(kap, co)
+    x = P.new()
+
+    for _ in range(a.warmup):
+        _, st = P.pcg_solve(b, x, RTOL, 100, v.VPS_SOLVE_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(a.steps):
+        _, st = P.pcg_solve(b, x, RTOL, 100, v.VPS_SOLVE_MIXED)
+        its.append(st.iterations)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / a.steps
+    out = {"metric": "smoother+V-cycle DoF/s (3D Q4, FP64 vs mixed); served-solve p50/p99 latency",
+           "value": N * a.steps / dt, "unit": "DoF/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "3D Poisson Q4, 64^3 cells (257^3 = 16974593 nodes), 16-mode Fourier rhs seed 1, "
+                                  "mixed-precision V-cycle CG to 1e-8", "dim": D, "degree": K, "level": L,
+                      "n_dofs": N, "rtol": RTOL, "parallelism": "single GPU"},
+           "mixed_solve": {"iterations": its[-1], "true_rel_residual": st.true_rel_residual, "ms": ms}}
+    if a.quick:
+        print(json.dumps(out))
+        return
+
+    # FP64 solve
+    x64 = P.new()
+    P.pcg_solve(b, x64, RTOL, 100, v.VPS_SOLVE_FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        _, s64 = P.pcg_solve(b, x64, RTOL, 100, v.VPS_SOLVE_FP64)
+    torch.cuda.synchronize()
+    ms64 = 1e3 * (time.perf_counter() - t0) / reps
+    diff = float((x - x64).norm() / x64.norm())
+    out["fp64_solve"] = {"iterations": s64.iterations, "ms": ms64, "dof_per_s": N / (ms64 / 1e3),
+                         "true_rel_residual": s64.true_rel_residual}
+    out["mixed_vs_fp64_rel_diff"] = diff
+    out["mixed_speedup"] = ms64 / ms
+
+    # smoothing step and V-cycle per precision (events on the problem's stream)
+    per = {}
+    for name, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
+        bb = b.to(dt_)
+        xx = torch.zeros_like(bb)
+        t_s = event_time(lambda: P.smoother_apply(bb, xx), stream, 10)
+        t_v = event_time(lambda: P.vcycle(bb, xx), stream, 10)
+        per[name] = {"smoothing_step_ms": 1e3 * t_s, "smoother_dof_per_s": N / t_s,
+                     "vcycle_ms": 1e3 * t_v, "vcycle_dof_per_s": N / t_v}
+    out["smoother_vcycle"] = per
+
+    # roofline of the dominant kernel: the FP32 colour pass on the finest level
+    info = P.info()
+    bb = b.to(torch.float32)
+    xx = torch.zeros_like(bb)
+    launches = 8 * 10
+    t_all = event_time(lambda: [P.color_pass(bb, xx, c) for c in range(8)], stream, 10) / 8
+    patches = sum(info.color_count[c] for c in range(8)) / 8
+    flops = colour_pass_flops(D, K) * patches
+    bytes_ = colour_pass_bytes(D, K, 4) * patches
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "colour_pass_3d_q4_fp32_traffic.json")
+    if os.path.exists(tf):
+        traffic = json.load(open(tf)).get("bytes_per_launch")
+    out["roofline"] = {"bound": "alu", "achieved": flops / t_all / 1e12, "peak": PEAK_FP32 / 1e12,
+                       "unit": "TFLOP/s", "frac": flops / t_all / PEAK_FP32, "traffic": traffic,
+                       "kernel": "colour_pass_kernel<3,4,float,false>", "avg_launch_us": 1e6 * t_all,
+                       "algorithmic_bytes_per_launch": bytes_, "algorithmic_gbps": bytes_ / t_all / 1e9,
+                       "flops_per_launch": flops, "launches_timed": launches}
+    xz = torch.zeros_like(b)
+    t64 = event_time(lambda: [P.color_pass(b, xz, c) for c in range(8)], stream, 5) / 8
+    out["roofline_fp64_colour_pass"] = {"achieved": flops / t64 / 1e12, "peak": PEAK_FP64 / 1e12,
+                                        "frac": flops / t64 / PEAK_FP64, "avg_launch_us": 1e6 * t64,
+                                        "algorithmic_gbps": colour_pass_bytes(D, K, 8) * patches / t64 / 1e9}
+    P.close()
+
+    if a.serve > 0:
+        out["serving"] = serving_run(v, a.serve)
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(N, its[-1] + 1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,589 @@
+// Matrix-free operator, residual, restriction and prolongation for gfx950.
+//
+// On a uniform Cartesian mesh the assembled operator is
+//   A = sum_dir (x)_a (A1 if a == dir else M1)      (Sec. 2.3 eq:mf, eq:tensorproduct)
+// with assembled 1D matrices A1 = sum_cells Ahat/h, M1 = sum_cells h Mhat, whose
+// row of a node only depends on the node's position inside its cell (the
+// "class" c = i mod k): 2k+1 band entries for a vertex, k+1 for a cell-interior
+// node.  The kernels apply A by sum factorisation over node tiles:
+//   stage x0: every thread reads one row of the input block (straight from
+//             global memory into registers) and produces M1 x and A1 x along
+//             x0 for the tile's outputs;
+//   stage x1: one column per thread, out of LDS, U = M1 (M1 x), V = A1 (M1 x)
+//             + M1 (A1 x) (3D) -- partial products reused as in the smoother;
+//   stage x2: one column per thread, y = A1 U + M1 V, written to global.
+// Each output node is owned by exactly one tile, so the result is
+// deterministic and needs no atomics (the paper resolves cell overlaps with
+// atomics; on a Cartesian mesh the node-tile form needs none).  Band classes
+// are compile-time inside the unrolled tile loops, so structural zeros are
+// skipped at compile time.
+//
+// Transfers use the same scheme with the 1D prolongation P1[i_f, J] =
+// phi^coarse_J(x^fine_i) (Sec. 2.1: embedding by interpolation) and its
+// transpose for restriction.
+//
+// All kernels here write interior nodes only; boundary entries of outputs are
+// zeroed by zero_boundary_kernel where the caller needs it.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace vps {
+
+static __constant__ DevTables<double> g_gtab64[kMaxDegree + 1];
+static __constant__ DevTables<float> g_gtab32[kMaxDegree + 1];
+
+template <typename T>
+__device__ __forceinline__ const DevTables<T>& gtab(int k);
+template <>
+__device__ __forceinline__ const DevTables<double>& gtab<double>(int k) { return g_gtab64[k]; }
+template <>
+__device__ __forceinline__ const DevTables<float>& gtab<float>(int k) { return g_gtab32[k]; }
+
+__device__ __forceinline__ bool is_bnd(long long i, long long n1d) { return i <= 0 || i >= n1d - 1; }
+
+// ----------------------------------------------------------------- operator
+
+// Cells per tile along (x0, x1, x2).
+template <int D, int K>
+struct OpShape {
+  static constexpr int C0 = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K <= 4 ? 8 : 4) : (16 / K > 1 ? 16 / K : 1);
+  static constexpr int C1 = D == 2 ? (K == 1 ? 8 : K <= 3 ? 4 : 2) : (K == 1 ? 4 : K <= 3 ? 2 : 1);
+  static constexpr int C2 = D == 3 ? C1 : 1;
+  static constexpr int NT = 128;
+};
+
+template <int D, int K, typename T, bool RESID>
+__global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* __restrict__ x, const T* __restrict__ b,
+                                                                     T* __restrict__ y, long long n1d, int tiles0,
+                                                                     int tiles1, T scale) {
+  using S = OpShape<D, K>;
+  constexpr int NT = S::NT, W = 2 * K + 1;
+  constexpr int TO0 = K * S::C0, TO1 = K * S::C1, TO2 = K * S::C2;
+  constexpr int TI0 = TO0 + K + 1, TI1 = TO1 + K + 1, TI2 = D == 3 ? TO2 + K + 1 : 1;
+  const DevTables<T>& tb = gtab<T>(K);
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles0;
+  const int ty = (blk / tiles0) % tiles1;
+  const int tz = D == 3 ? blk / (tiles0 * tiles1) : 0;
+  const long long o0 = (long long)tx * TO0, o1 = (long long)ty * TO1, o2 = (long long)tz * TO2;  // first output node
+  const long long n1d2 = n1d * n1d;
+  const int tid = threadIdx.x;
+
+  __shared__ T PM[TI2 * TI1 * TO0];
+  __shared__ T PA[TI2 * TI1 * TO0];
+
+  // stage x0: rows (z, y) of the input block
+  for (int task = tid; task < TI2 * TI1; task += NT) {
+    const int zl = task / TI1, yl = task - zl * TI1;
+    const long long gz = D == 3 ? o2 - K + zl : 0, gy = o1 - K + yl;
+    T in[TI0];
+    const bool row_ok = !is_bnd(gy, n1d) && (D == 2 || !is_bnd(gz, n1d));
+    const long long rb = (D == 3 ? gz * n1d2 : 0) + gy * n1d;
+#pragma unroll
+    for (int j = 0; j < TI0; ++j) {
+      const long long gx = o0 - K + j;
+      in[j] = (row_ok && !is_bnd(gx, n1d)) ? x[rb + gx] : T(0);
+    }
+#pragma unroll
+    for (int xo = 0; xo < TO0; ++xo) {
+      const int c = xo % K;
+      T sm = T(0), sa = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        if (c > 0 && t < K) continue;
+        sm = fma(tb.Mb[c * W + t], in[xo - c + t], sm);
+        sa = fma(tb.Ab[c * W + t], in[xo - c + t], sa);
+      }
+      PM[(zl * TI1 + yl) * TO0 + xo] = sm;
+      PA[(zl * TI1 + yl) * TO0 + xo] = sa;
+    }
+  }
+  __syncthreads();
+
+  if constexpr (D == 2) {
+    // stage x1: columns xo, outputs y = A1 (M1 x) + M1 (A1 x)
+    for (int task = tid; task < TO0; task += NT) {
+      const int xo = task;
+      T pm[TI1], pa[TI1];
+#pragma unroll
+      for (int j = 0; j < TI1; ++j) {
+        pm[j] = PM[j * TO0 + xo];
+        pa[j] = PA[j * TO0 + xo];
+      }
+      const long long gx = o0 + xo;
+#pragma unroll
+      for (int yo = 0; yo < TO1; ++yo) {
+        const int c = yo % K;
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          if (c > 0 && t < K) continue;
+          s = fma(tb.Ab[c * W + t], pm[yo - c + t], s);
+          s = fma(tb.Mb[c * W + t], pa[yo - c + t], s);
+        }
+        const long long gy = o1 + yo;
+        if (!is_bnd(gx, n1d) && !is_bnd(gy, n1d)) {
+          const long long g = gy * n1d + gx;
+          y[g] = RESID ? b[g] - scale * s : scale * s;
+        }
+      }
+    }
+  } else {
+    __shared__ T U[TI2 * TO1 * TO0];
+    __shared__ T V[TI2 * TO1 * TO0];
+    // stage x1: columns (z, xo)
+    for (int task = tid; task < TI2 * TO0; task += NT) {
+      const int zl = task / TO0, xo = task - zl * TO0;
+      T pm[TI1], pa[TI1];
+#pragma unroll
+      for (int j = 0; j < TI1; ++j) {
+        pm[j] = PM[(zl * TI1 + j) * TO0 + xo];
+        pa[j] = PA[(zl * TI1 + j) * TO0 + xo];
+      }
+#pragma unroll
+      for (int yo = 0; yo < TO1; ++yo) {
+        const int c = yo % K;
+        T su = T(0), sv = T(0);
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          if (c > 0 && t < K) continue;
+          su = fma(tb.Mb[c * W + t], pm[yo - c + t], su);
+          sv = fma(tb.Ab[c * W + t], pm[yo - c + t], sv);
+          sv = fma(tb.Mb[c * W + t], pa[yo - c + t], sv);
+        }
+        U[(zl * TO1 + yo) * TO0 + xo] = su;
+        V[(zl * TO1 + yo) * TO0 + xo] = sv;
+      }
+    }
+    __syncthreads();
+    // stage x2: columns (yo, xo); y = A1 U + M1 V
+    for (int task = tid; task < TO1 * TO0; task += NT) {
+      const int yo = task / TO0, xo = task - yo * TO0;
+      T u[TI2], v[TI2];
+#pragma unroll
+      for (int j = 0; j < TI2; ++j) {
+        u[j] = U[(j * TO1 + yo) * TO0 + xo];
+        v[j] = V[(j * TO1 + yo) * TO0 + xo];
+      }
+      const long long gx = o0 + xo, gy = o1 + yo;
+      const bool col_ok = !is_bnd(gx, n1d) && !is_bnd(gy, n1d);
+#pragma unroll
+      for (int zo = 0; zo < TO2; ++zo) {
+        const int c = zo % K;
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          if (c > 0 && t < K) continue;
+          s = fma(tb.Ab[c * W + t], u[zo - c + t], s);
+          s = fma(tb.Mb[c * W + t], v[zo - c + t], s);
+        }
+        const long long gz = o2 + zo;
+        if (col_ok && !is_bnd(gz, n1d)) {
+          const long long g = gz * n1d2 + gy * n1d + gx;
+          y[g] = RESID ? b[g] - scale * s : scale * s;
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------- prolongation
+
+// Coarse cells per tile.
+template <int D, int K>
+struct ProShape {
+  static constexpr int C = K == 1 ? (D == 2 ? 16 : 4) : K == 2 ? (D == 2 ? 8 : 2) : (D == 2 ? 4 : 1);
+  static constexpr int NT = 128;
+};
+
+// x_fine += P e_coarse.  Tile: coarse cells [C t, C (t+1)) per axis, fine outputs
+// [2kC t, 2kC (t+1)), coarse inputs [kC t, kC (t+1)].
+template <int D, int K, typename T>
+__global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(const T* __restrict__ e, T* __restrict__ xf,
+                                                                          long long n1dc, long long n1df, int tiles) {
+  constexpr int C = ProShape<D, K>::C, NT = ProShape<D, K>::NT;
+  constexpr int TI = K * C + 1, TO = 2 * K * C, TIz = D == 3 ? TI : 1;
+  constexpr int NP = K + 1;
+  const DevTables<T>& tb = gtab<T>(K);
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
+  const long long c0 = (long long)tx * K * C, c1 = (long long)ty * K * C, c2 = (long long)tz * K * C;
+  const long long f0 = 2 * c0, f1 = 2 * c1, f2 = 2 * c2;
+  const int tid = threadIdx.x;
+  const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
+  __shared__ T T1[TIz * TI * TO];
+  // stage x0: coarse rows
+  for (int task = tid; task < TIz * TI; task += NT) {
+    const int zl = task / TI, yl = task - zl * TI;
+    const long long gz = D == 3 ? c2 + zl : 0, gy = c1 + yl;
+    const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && (D == 2 || (gz < n1dc && !is_bnd(gz, n1dc)));
+    T in[TI];
+#pragma unroll
+    for (int j = 0; j < TI; ++j) {
+      const long long gx = c0 + j;
+      in[j] = (ok && gx < n1dc && !is_bnd(gx, n1dc)) ? e[(D == 3 ? gz * nc2 : 0) + gy * n1dc + gx] : T(0);
+    }
+#pragma unroll
+    for (int xo = 0; xo < TO; ++xo) {
+      const int cc = xo / (2 * K), q = xo % (2 * K);
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        if (q == 0 && a > 0) continue;
+        s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+      }
+      T1[(zl * TI + yl) * TO + xo] = s;
+    }
+  }
+  __syncthreads();
+  if constexpr (D == 2) {
+    for (int task = tid; task < TO; task += NT) {
+      const int xo = task;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T1[j * TO + xo];
+      const long long gx = f0 + xo;
+#pragma unroll
+      for (int yo = 0; yo < TO; ++yo) {
+        const int cc = yo / (2 * K), q = yo % (2 * K);
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;
+          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+        }
+        const long long gy = f1 + yo;
+        if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] += s;
+      }
+    }
+  } else {
+    __shared__ T T2[TI * TO * TO];
+    for (int task = tid; task < TI * TO; task += NT) {
+      const int zl = task / TO, xo = task - zl * TO;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T1[(zl * TI + j) * TO + xo];
+#pragma unroll
+      for (int yo = 0; yo < TO; ++yo) {
+        const int cc = yo / (2 * K), q = yo % (2 * K);
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;
+          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+        }
+        T2[(zl * TO + yo) * TO + xo] = s;
+      }
+    }
+    __syncthreads();
+    for (int task = tid; task < TO * TO; task += NT) {
+      const int yo = task / TO, xo = task - yo * TO;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
+      const long long gx = f0 + xo, gy = f1 + yo;
+      const bool ok = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df);
+#pragma unroll
+      for (int zo = 0; zo < TO; ++zo) {
+        const int cc = zo / (2 * K), q = zo % (2 * K);
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;
+          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+        }
+        const long long gz = f2 + zo;
+        if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] += s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- restriction
+
+template <int D, int K>
+struct ResShape {
+  static constexpr int C = K == 1 ? (D == 2 ? 16 : 4) : K == 2 ? (D == 2 ? 8 : 2) : (D == 2 ? 4 : 1);
+  static constexpr int NT = 128;
+};
+
+// r_coarse = P^T r_fine.  Tile: coarse outputs [kC t, kC (t+1)) per axis; fine
+// inputs [2kC t - 2k, 2kC (t+1)].
+template <int D, int K, typename T>
+__global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(const T* __restrict__ rf, T* __restrict__ rc,
+                                                                           long long n1dc, long long n1df, int tiles) {
+  constexpr int C = ResShape<D, K>::C, NT = ResShape<D, K>::NT;
+  constexpr int TO = K * C, TI = 2 * K * C + 2 * K + 1, TIz = D == 3 ? TI : 1, RW = 4 * K + 1;
+  const DevTables<T>& tb = gtab<T>(K);
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
+  const long long c0 = (long long)tx * TO, c1 = (long long)ty * TO, c2 = (long long)tz * TO;
+  const long long f0 = 2 * c0 - 2 * K, f1 = 2 * c1 - 2 * K, f2 = 2 * c2 - 2 * K;
+  const int tid = threadIdx.x;
+  const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
+  __shared__ T T1[TIz * TI * TO];
+  for (int task = tid; task < TIz * TI; task += NT) {
+    const int zl = task / TI, yl = task - zl * TI;
+    const long long gz = D == 3 ? f2 + zl : 0, gy = f1 + yl;
+    const bool ok = !is_bnd(gy, n1df) && (D == 2 || !is_bnd(gz, n1df));
+    T in[TI];
+#pragma unroll
+    for (int j = 0; j < TI; ++j) {
+      const long long gx = f0 + j;
+      in[j] = (ok && !is_bnd(gx, n1df)) ? rf[(D == 3 ? gz * nf2 : 0) + gy * n1df + gx] : T(0);
+    }
+#pragma unroll
+    for (int xo = 0; xo < TO; ++xo) {
+      const int a = xo % K, cc = xo / K;
+      T s = T(0);
+#pragma unroll
+      for (int t = 0; t < RW; ++t) {
+        if (a > 0 && t < 2 * K) continue;
+        s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+      }
+      T1[(zl * TI + yl) * TO + xo] = s;
+    }
+  }
+  __syncthreads();
+  if constexpr (D == 2) {
+    for (int task = tid; task < TO; task += NT) {
+      const int xo = task;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T1[j * TO + xo];
+      const long long gx = c0 + xo;
+#pragma unroll
+      for (int yo = 0; yo < TO; ++yo) {
+        const int a = yo % K, cc = yo / K;
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          if (a > 0 && t < 2 * K) continue;
+          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+        }
+        const long long gy = c1 + yo;
+        if (!is_bnd(gx, n1dc) && !is_bnd(gy, n1dc)) rc[gy * n1dc + gx] = s;
+      }
+    }
+  } else {
+    __shared__ T T2[TI * TO * TO];
+    for (int task = tid; task < TI * TO; task += NT) {
+      const int zl = task / TO, xo = task - zl * TO;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T1[(zl * TI + j) * TO + xo];
+#pragma unroll
+      for (int yo = 0; yo < TO; ++yo) {
+        const int a = yo % K, cc = yo / K;
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          if (a > 0 && t < 2 * K) continue;
+          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+        }
+        T2[(zl * TO + yo) * TO + xo] = s;
+      }
+    }
+    __syncthreads();
+    for (int task = tid; task < TO * TO; task += NT) {
+      const int yo = task / TO, xo = task - yo * TO;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
+      const long long gx = c0 + xo, gy = c1 + yo;
+      const bool ok = !is_bnd(gx, n1dc) && !is_bnd(gy, n1dc);
+#pragma unroll
+      for (int zo = 0; zo < TO; ++zo) {
+        const int a = zo % K, cc = zo / K;
+        T s = T(0);
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          if (a > 0 && t < 2 * K) continue;
+          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+        }
+        const long long gz = c2 + zo;
+        if (ok && !is_bnd(gz, n1dc)) rc[gz * nc2 + gy * n1dc + gx] = s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------- boundary and rhs
+
+// Zero every boundary node: thread per node of the d-1 dimensional faces.
+template <typename T>
+__global__ void zero_boundary_kernel(T* __restrict__ y, int dim, long long n1d) {
+  const long long faces = dim == 2 ? n1d : n1d * n1d;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= faces) return;
+  const long long n2 = n1d * n1d;
+  for (int a = 0; a < dim; ++a) {
+    // t enumerates the other axes; the boundary planes are index 0 and n1d-1 along axis a
+    long long u = dim == 2 ? t : t % n1d, v = dim == 2 ? 0 : t / n1d;
+    for (int side = 0; side < 2; ++side) {
+      const long long fixed = side ? n1d - 1 : 0;
+      long long idx;
+      if (dim == 2)
+        idx = a == 0 ? u * n1d + fixed : fixed * n1d + u;
+      else
+        idx = a == 0 ? (v * n1d + u) * n1d + fixed : a == 1 ? (v * n1d + fixed) * n1d + u : (fixed * n1d + v) * n1d + u;
+      y[idx] = T(0);
+    }
+    (void)n2;
+  }
+}
+
+// b[node] = sum_m coef[m] prod_a G[(m*dim + a)*n1d + i_a], interior nodes; boundary 0.
+template <typename T>
+__global__ void rhs_separable_kernel(T* __restrict__ b, const double* __restrict__ G, const double* __restrict__ coef,
+                                     int nterms, int dim, long long n1d, long long ntot) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ntot) return;
+  const long long i0 = idx % n1d, r = idx / n1d;
+  const long long i1 = r % n1d, i2 = dim == 3 ? r / n1d : 0;
+  if (is_bnd(i0, n1d) || is_bnd(i1, n1d) || (dim == 3 && is_bnd(i2, n1d))) {
+    b[idx] = T(0);
+    return;
+  }
+  double s = 0.0;
+  for (int m = 0; m < nterms; ++m) {
+    const double* g = G + (long long)m * dim * n1d;
+    double v = coef[m] * g[i0] * g[n1d + i1];
+    if (dim == 3) v *= g[2 * n1d + i2];
+    s += v;
+  }
+  b[idx] = (T)s;
+}
+
+// ------------------------------------------------------------------ launchers
+
+namespace {
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <int D, int K, typename T>
+hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+  using S = OpShape<D, K>;
+  const int t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1), t2 = D == 3 ? ceil_div(g.ncells, S::C2) : 1;
+  const long long blocks = (long long)t0 * t1 * t2;
+  const T scale = (T)(D == 3 ? g.h : 1.0);  // A_h = h^(d-2) A_1
+  if (b)
+    hipLaunchKernelGGL((op_tile_kernel<D, K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
+                       (const T*)b, (T*)y, g.n1d, t0, t1, scale);
+  else
+    hipLaunchKernelGGL((op_tile_kernel<D, K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
+                       (const T*)nullptr, (T*)y, g.n1d, t0, t1, scale);
+  return hipGetLastError();
+}
+
+template <int D, int K, typename T>
+hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_t st) {
+  using S = ProShape<D, K>;
+  const long long ncc = fine.ncells / 2;
+  const int tiles = ceil_div(ncc, S::C);
+  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
+  const long long n1dc = (long long)K * ncc + 1;
+  hipLaunchKernelGGL((prolong_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf,
+                     n1dc, fine.n1d, tiles);
+  return hipGetLastError();
+}
+
+template <int D, int K, typename T>
+hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st) {
+  using S = ResShape<D, K>;
+  const long long ncc = fine.ncells / 2;
+  const int tiles = ceil_div(ncc, S::C);
+  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
+  const long long n1dc = (long long)K * ncc + 1;
+  hipLaunchKernelGGL((restrict_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)rf, (T*)rc,
+                     n1dc, fine.n1d, tiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define VPS_DISPATCH(FN, G, PREC, ...)                                                   \
+  do {                                                                                   \
+    const int d_ = (G).dim, k_ = (G).k;                                                  \
+    switch (d_ * 100 + k_ * 10 + (PREC)) {                                               \
+      case 210: return FN<2, 1, double>(G, __VA_ARGS__);                                 \
+      case 211: return FN<2, 1, float>(G, __VA_ARGS__);                                  \
+      case 220: return FN<2, 2, double>(G, __VA_ARGS__);                                 \
+      case 221: return FN<2, 2, float>(G, __VA_ARGS__);                                  \
+      case 230: return FN<2, 3, double>(G, __VA_ARGS__);                                 \
+      case 231: return FN<2, 3, float>(G, __VA_ARGS__);                                  \
+      case 240: return FN<2, 4, double>(G, __VA_ARGS__);                                 \
+      case 241: return FN<2, 4, float>(G, __VA_ARGS__);                                  \
+      case 250: return FN<2, 5, double>(G, __VA_ARGS__);                                 \
+      case 251: return FN<2, 5, float>(G, __VA_ARGS__);                                  \
+      case 260: return FN<2, 6, double>(G, __VA_ARGS__);                                 \
+      case 261: return FN<2, 6, float>(G, __VA_ARGS__);                                  \
+      case 270: return FN<2, 7, double>(G, __VA_ARGS__);                                 \
+      case 271: return FN<2, 7, float>(G, __VA_ARGS__);                                  \
+      case 310: return FN<3, 1, double>(G, __VA_ARGS__);                                 \
+      case 311: return FN<3, 1, float>(G, __VA_ARGS__);                                  \
+      case 320: return FN<3, 2, double>(G, __VA_ARGS__);                                 \
+      case 321: return FN<3, 2, float>(G, __VA_ARGS__);                                  \
+      case 330: return FN<3, 3, double>(G, __VA_ARGS__);                                 \
+      case 331: return FN<3, 3, float>(G, __VA_ARGS__);                                  \
+      case 340: return FN<3, 4, double>(G, __VA_ARGS__);                                 \
+      case 341: return FN<3, 4, float>(G, __VA_ARGS__);                                  \
+      case 350: return FN<3, 5, double>(G, __VA_ARGS__);                                 \
+      case 351: return FN<3, 5, float>(G, __VA_ARGS__);                                  \
+      case 360: return FN<3, 6, double>(G, __VA_ARGS__);                                 \
+      case 361: return FN<3, 6, float>(G, __VA_ARGS__);                                  \
+      case 370: return FN<3, 7, double>(G, __VA_ARGS__);                                 \
+      case 371: return FN<3, 7, float>(G, __VA_ARGS__);                                  \
+    }                                                                                    \
+    return hipErrorInvalidValue;                                                         \
+  } while (0)
+
+hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b, void* y, hipStream_t st) {
+  VPS_DISPATCH(op_launch, g, prec, x, b, y, st);
+}
+
+hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st) {
+  VPS_DISPATCH(pro_launch, fine, prec, e, xf, st);
+}
+
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, hipStream_t st) {
+  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st);
+}
+
+hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st) {
+  const long long faces = g.dim == 2 ? g.n1d : g.n1d * g.n1d;
+  const unsigned blocks = (unsigned)((faces + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(zero_boundary_kernel<double>, dim3(blocks), dim3(256), 0, st, (double*)y, g.dim, g.n1d);
+  else
+    hipLaunchKernelGGL(zero_boundary_kernel<float>, dim3(blocks), dim3(256), 0, st, (float*)y, g.dim, g.n1d);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const double* G, const double* coef, void* b,
+                                hipStream_t st) {
+  long long ntot = 1;
+  for (int a = 0; a < g.dim; ++a) ntot *= g.n1d;
+  const unsigned blocks = (unsigned)((ntot + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(rhs_separable_kernel<double>, dim3(blocks), dim3(256), 0, st, (double*)b, G, coef, nterms,
+                       g.dim, g.n1d, ntot);
+  else
+    hipLaunchKernelGGL(rhs_separable_kernel<float>, dim3(blocks), dim3(256), 0, st, (float*)b, G, coef, nterms, g.dim,
+                       g.n1d, ntot);
+  return hipGetLastError();
+}
+
+hipError_t init_grid_tables() {
+  static DevTables<double> h64[kMaxDegree + 1];
+  static DevTables<float> h32[kMaxDegree + 1];
+  for (int k = 1; k <= kMaxDegree; ++k) {
+    fill_dev_tables(k, h64[k]);
+    fill_dev_tables(k, h32[k]);
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_gtab64), h64, sizeof(h64));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_gtab32), h32, sizeof(h32));
+}
+
+}  // namespace vps

@@ -1,0 +1,54 @@
+// Launch functions of the device code (HIP translation units), called by the
+// host-side library.  All launches are asynchronous on the given stream and
+// return the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace vps {
+
+// Scalar slots of the CG scalar block (device memory, doubles).
+enum : int {
+  kScRZ = 0,     // r.z of the current iterate
+  kScPQ = 10,    // p.A p                         (written together with slot 11)
+  kScRR = 2,     // r.r after the update          (written together with kScRZOld)
+  kScRZOld = 3,  // r_new . z_old (flexible beta)
+  kScRZNew = 4,  // r_new . z_new                 (written together with kScAux)
+  kScAux = 5,
+  kScBeta = 6,
+  kScBB = 7,     // b.b
+  kScTrue = 8,   // true residual norm squared    (written together with kScAux2)
+  kScAux2 = 9,
+  kScCount = 16
+};
+
+hipError_t init_smoother_tables();
+hipError_t init_grid_tables();
+
+// smoother.hip
+hipError_t launch_colour_pass(const LevelGeom& g, int prec, bool additive, int colour, const void* b, void* x,
+                              hipStream_t st);
+
+// grid.hip (interior outputs only)
+hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b_or_null, void* y, hipStream_t st);
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, hipStream_t st);
+hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st);
+hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);
+hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const double* G, const double* coef, void* b,
+                                hipStream_t st);
+
+// vector.hip
+int reduction_parts();  // partial slots the reductions use (pairs: 2x this many doubles)
+hipError_t launch_fill(int prec, void* x, long long n, double v, hipStream_t st);
+hipError_t launch_cast(int from_prec, const void* src, void* dst, long long n, hipStream_t st);
+hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, double* dst, double* partial,
+                                     double* out, int* bad, hipStream_t st);
+hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, long long n,
+                       double* partial, double* out, hipStream_t st);
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
+                            double* sc, double* partial, hipStream_t st);
+hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st);
+hipError_t launch_cg_direction(double* p, const double* z, long long n, const double* sc, hipStream_t st);
+
+}  // namespace vps

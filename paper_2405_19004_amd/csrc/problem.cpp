@@ -1,0 +1,348 @@
+// Level hierarchy, V-cycle (Alg. 1) and preconditioned CG drivers.  The host
+// only sequences launches (Sec. 3: building blocks launched one after the
+// other); all vectors stay resident on the device during a solve (Sec. 3.1).
+#include "problem.hpp"
+
+#include <cmath>
+#include <cstring>
+
+#include "kernels.hpp"
+
+#define VPS_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return Status{-3, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define VPS_TRY(expr)                 \
+  do {                                \
+    Status s_ = (expr);               \
+    if (s_.code != 0) return s_;      \
+  } while (0)
+
+namespace vps {
+
+enum { kMult = 0, kAdd = 1 };
+
+long long level_nodes(int dim, int k, int level) {
+  long long n = (long long)k * (1LL << level) + 1;
+  return dim == 2 ? n * n : n * n * n;
+}
+
+LevelGeom make_geom(int dim, int k, int level) {
+  LevelGeom g;
+  g.dim = dim;
+  g.k = k;
+  g.level = level;
+  g.ncells = 1LL << level;
+  g.n1d = (long long)k * g.ncells + 1;
+  g.h = 1.0 / (double)g.ncells;
+  return g;
+}
+
+namespace {
+
+struct Plan {
+  // byte sizes of every allocation in creation order
+  std::vector<size_t> sizes;
+};
+
+// The allocation plan is the single source of the footprint and of create_problem.
+Plan plan(int dim, int k, int L, unsigned flags) {
+  Plan pl;
+  const bool h64 = flags & 0x1u, h32 = flags & 0x2u, solver = !(flags & 0x4u);
+  for (int lvl = 1; lvl <= L; ++lvl) {
+    const size_t N = (size_t)level_nodes(dim, k, lvl);
+    for (int prec = 0; prec < 2; ++prec) {
+      const bool want = prec == 0 ? h64 : h32;
+      if (!want) continue;
+      const size_t es = prec == 0 ? 8 : 4;
+      const bool bx = lvl < L || prec == 1;
+      if (bx) {
+        pl.sizes.push_back(N * es);  // b
+        pl.sizes.push_back(N * es);  // x
+      }
+      if (lvl >= 2) pl.sizes.push_back(N * es);  // r
+    }
+  }
+  if (h32) {
+    const size_t N1 = (size_t)level_nodes(dim, k, 1);
+    pl.sizes.push_back(N1 * 8);
+    pl.sizes.push_back(N1 * 8);
+  }
+  if (solver) {
+    const size_t N = (size_t)level_nodes(dim, k, L);
+    for (int i = 0; i < 4; ++i) pl.sizes.push_back(N * 8);  // r z p q
+  }
+  pl.sizes.push_back(kScCount * 8);
+  pl.sizes.push_back(2 * (size_t)reduction_parts() * 8);
+  pl.sizes.push_back(256);  // flag
+  return pl;
+}
+
+size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t footprint_bytes(int dim, int degree, int L, unsigned flags) {
+  Plan pl = plan(dim, degree, L, flags);
+  size_t t = 0;
+  for (size_t s : pl.sizes) t += round_up(s);
+  return t;
+}
+
+Problem::~Problem() {
+  if (stream) hipStreamSynchronize(stream);
+  for (void* a : allocs) hipFree(a);
+  if (host_sc) hipHostFree(host_sc);
+  if (host_bad) hipHostFree(host_bad);
+}
+
+bool Problem::has(int prec) const { return prec == 0 ? (flags & 0x1u) : (flags & 0x2u); }
+
+Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Problem** out) {
+  static bool tables_ready = false;
+  if (!tables_ready) {
+    VPS_HIP(init_smoother_tables());
+    VPS_HIP(init_grid_tables());
+    tables_ready = true;
+  }
+  Problem* p = new Problem();
+  p->dim = dim;
+  p->k = k;
+  p->L = L;
+  p->flags = flags;
+  p->stream = st;
+  p->post_same_order = flags & 0x8u;
+  p->lv.resize(L + 1);
+  Plan pl = plan(dim, k, L, flags);
+  std::vector<void*> ptrs;
+  for (size_t s : pl.sizes) {
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, round_up(s));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      delete p;
+      return Status{-2, "hipMalloc of " + std::to_string(round_up(s)) + " bytes failed"};
+    }
+    p->allocs.push_back(d);
+    p->bytes += round_up(s);
+    e = hipMemsetAsync(d, 0, round_up(s), st);
+    if (e != hipSuccess) {
+      delete p;
+      return Status{-3, std::string("hipMemsetAsync: ") + hipGetErrorString(e)};
+    }
+  }
+  // hand out in plan order
+  size_t idx = 0;
+  const bool h64 = flags & 0x1u, h32 = flags & 0x2u, solver = !(flags & 0x4u);
+  for (int lvl = 1; lvl <= L; ++lvl) {
+    LevelBuffers& B = p->lv[lvl];
+    B.g = make_geom(dim, k, lvl);
+    B.N = level_nodes(dim, k, lvl);
+    for (int prec = 0; prec < 2; ++prec) {
+      const bool want = prec == 0 ? h64 : h32;
+      if (!want) continue;
+      const bool bx = lvl < L || prec == 1;
+      if (bx) {
+        B.b[prec] = p->allocs[idx++];
+        B.x[prec] = p->allocs[idx++];
+      }
+      if (lvl >= 2) B.r[prec] = p->allocs[idx++];
+    }
+  }
+  if (h32) {
+    p->c64_b = (double*)p->allocs[idx++];
+    p->c64_x = (double*)p->allocs[idx++];
+  }
+  if (solver) {
+    p->r = (double*)p->allocs[idx++];
+    p->z = (double*)p->allocs[idx++];
+    p->p = (double*)p->allocs[idx++];
+    p->q = (double*)p->allocs[idx++];
+  }
+  p->sc = (double*)p->allocs[idx++];
+  p->partial = (double*)p->allocs[idx++];
+  p->bad = (int*)p->allocs[idx++];
+  if (hipHostMalloc((void**)&p->host_sc, kScCount * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->host_bad, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return Status{-2, "hipHostMalloc failed"};
+  }
+  VPS_HIP(hipStreamSynchronize(st));
+  *out = p;
+  return Status::ok();
+}
+
+// ------------------------------------------------------------------ smoothing
+
+Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x) {
+  VPS_HIP(launch_colour_pass(p->geom(level), prec, mode == kAdd, colour, b, x, p->stream));
+  return Status::ok();
+}
+
+Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x) {
+  const int nc = 1 << p->dim;
+  for (int i = 0; i < nc; ++i) {
+    const int c = reverse ? nc - 1 - i : i;
+    VPS_TRY(colour_pass(p, level, prec, mode, c, b, x));
+  }
+  return Status::ok();
+}
+
+Status coarse_solve(Problem* p, int prec, const void* b, void* x) {
+  const LevelGeom& g = p->geom(1);
+  const long long N = p->lv[1].N;
+  if (prec == 0) {
+    VPS_HIP(launch_fill(0, x, N, 0.0, p->stream));
+    VPS_HIP(launch_colour_pass(g, 0, false, 0, b, x, p->stream));
+    return Status::ok();
+  }
+  if (!p->c64_b) return Status{-1, "FP32 coarse solve needs the FP32 hierarchy"};
+  VPS_HIP(launch_cast(1, b, p->c64_b, N, p->stream));
+  VPS_HIP(launch_fill(0, p->c64_x, N, 0.0, p->stream));
+  VPS_HIP(launch_colour_pass(g, 0, false, 0, p->c64_b, p->c64_x, p->stream));
+  VPS_HIP(launch_cast(0, p->c64_x, x, N, p->stream));
+  return Status::ok();
+}
+
+Status vcycle(Problem* p, int prec, const void* bL, void* xL) {
+  if (!p->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
+  const int L = p->L;
+  if (L == 1) return coarse_solve(p, prec, bL, xL);
+  const bool post_rev = !p->post_same_order;
+  // descend
+  for (int lvl = L; lvl >= 2; --lvl) {
+    const void* b = lvl == L ? bL : p->lv[lvl].b[prec];
+    void* x = lvl == L ? xL : p->lv[lvl].x[prec];
+    if (lvl < L) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
+    VPS_TRY(smoother(p, lvl, prec, kMult, false, b, x));
+    VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
+    VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->stream));
+  }
+  VPS_TRY(coarse_solve(p, prec, p->lv[1].b[prec], p->lv[1].x[prec]));
+  // ascend
+  for (int lvl = 2; lvl <= L; ++lvl) {
+    const void* b = lvl == L ? bL : p->lv[lvl].b[prec];
+    void* x = lvl == L ? xL : p->lv[lvl].x[prec];
+    VPS_HIP(launch_prolongate_add(p->geom(lvl), prec, p->lv[lvl - 1].x[prec], x, p->stream));
+    VPS_TRY(smoother(p, lvl, prec, kMult, post_rev, b, x));
+  }
+  return Status::ok();
+}
+
+// ------------------------------------------------------------------------ CG
+
+namespace {
+
+Status precondition(Problem* p, int mode, const double* r, double* z) {
+  const long long N = p->lv[p->L].N;
+  if (mode == 0) {
+    VPS_HIP(launch_fill(0, z, N, 0.0, p->stream));
+    return vcycle(p, 0, r, z);
+  }
+  LevelBuffers& B = p->lv[p->L];
+  VPS_HIP(launch_cast(0, r, B.b[1], N, p->stream));
+  VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
+  VPS_TRY(vcycle(p, 1, B.b[1], B.x[1]));
+  VPS_HIP(launch_cast(1, B.x[1], z, N, p->stream));
+  return Status::ok();
+}
+
+}  // namespace
+
+Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) {
+  if (!p->r) return Status{-1, "problem was created without solver vectors"};
+  if (!p->has(mode == 0 ? 0 : 1)) return Status{-1, "solve mode needs the matching hierarchy flag"};
+  const long long N = p->lv[p->L].N;
+  *cs = CgState();
+  VPS_HIP(hipMemsetAsync(p->bad, 0, sizeof(int), p->stream));
+  VPS_HIP(launch_copy_interior_norm(p->dim, p->lv[p->L].g.n1d, b, p->r, p->partial, p->sc + kScBB, p->bad, p->stream));
+  VPS_HIP(launch_fill(0, x, N, 0.0, p->stream));
+  VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  VPS_HIP(hipMemcpyAsync(p->host_bad, p->bad, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  VPS_HIP(hipStreamSynchronize(p->stream));
+  cs->bb = p->host_sc[kScBB];
+  if (*p->host_bad || !std::isfinite(cs->bb)) {
+    cs->done = true;
+    cs->stats.status = -6;
+    return Status::ok();
+  }
+  if (cs->bb == 0.0) {
+    cs->done = true;
+    cs->stats.rel_residual = 0.0;
+    return Status::ok();
+  }
+  VPS_TRY(precondition(p, mode, p->r, p->z));
+  VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
+  VPS_HIP(launch_cg_beta(p->sc, 0, p->stream));  // rz <- rz_new (beta unused here)
+  VPS_HIP(hipMemcpyAsync(p->p, p->z, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  return Status::ok();
+}
+
+Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
+  (void)mode;
+  const long long N = p->lv[p->L].N;
+  VPS_HIP(launch_operator(p->geom(p->L), 0, p->p, nullptr, p->q, p->stream));
+  VPS_HIP(launch_dot2(p->p, p->q, nullptr, nullptr, N, p->partial, p->sc + kScPQ, p->stream));
+  VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, N, p->sc, p->partial, p->stream));
+  VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  (void)cs;
+  return Status::ok();
+}
+
+Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
+  const long long N = p->lv[p->L].N;
+  const double pq = p->host_sc[kScPQ], rz = p->host_sc[kScRZ], rr = p->host_sc[kScRR];
+  cs->it += 1;
+  cs->stats.iterations = cs->it;
+  if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rz) || !std::isfinite(rr)) {
+    cs->done = true;
+    cs->stats.status = -5;
+    return Status::ok();
+  }
+  cs->rel = std::sqrt(rr / cs->bb);
+  cs->stats.rel_residual = cs->rel;
+  if (cs->rel <= rtol) {
+    cs->done = true;
+    cs->stats.status = 0;
+    return Status::ok();
+  }
+  if (cs->it >= maxit) {
+    cs->done = true;
+    cs->stats.status = -4;
+    return Status::ok();
+  }
+  VPS_TRY(precondition(p, mode, p->r, p->z));
+  VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
+  VPS_HIP(launch_cg_beta(p->sc, mode == 1 ? 1 : 0, p->stream));
+  VPS_HIP(launch_cg_direction(p->p, p->z, N, p->sc, p->stream));
+  return Status::ok();
+}
+
+Status pcg_end(Problem* p, const double* b, double* x, CgState* cs) {
+  const long long N = p->lv[p->L].N;
+  if (cs->stats.status == -6 || cs->bb == 0.0) return Status::ok();
+  VPS_HIP(launch_operator(p->geom(p->L), 0, x, b, p->q, p->stream));  // q = b - A x (interior)
+  VPS_HIP(launch_dot2(p->q, p->q, nullptr, nullptr, N, p->partial, p->sc + kScTrue, p->stream));
+  VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  VPS_HIP(hipStreamSynchronize(p->stream));
+  cs->stats.true_rel_residual = std::sqrt(p->host_sc[kScTrue] / cs->bb);
+  return Status::ok();
+}
+
+Status pcg(Problem* p, int mode, const double* b, double* x, double rtol, int maxit, SolveStats* out) {
+  CgState cs;
+  VPS_TRY(pcg_begin(p, mode, b, x, &cs));
+  while (!cs.done) {
+    VPS_TRY(pcg_iterate_launch(p, mode, x, &cs));
+    VPS_HIP(hipStreamSynchronize(p->stream));
+    VPS_TRY(pcg_iterate_finish(p, mode, rtol, maxit, &cs));
+  }
+  VPS_TRY(pcg_end(p, b, x, &cs));
+  if (out) *out = cs.stats;
+  return Status::ok();
+}
+
+}  // namespace vps

@@ -1,0 +1,84 @@
+// Host-side state of one Poisson problem: the level hierarchy, device scratch
+// and the solver drivers (V-cycle, CG).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+
+namespace vps {
+
+struct Status {
+  int code = 0;
+  std::string msg;
+  static Status ok() { return {}; }
+};
+
+struct LevelBuffers {
+  LevelGeom g{};
+  long long N = 0;                  // nodes on the level
+  void* b[2] = {nullptr, nullptr};  // V-cycle right-hand side per precision (levels < L; FP32 also L)
+  void* x[2] = {nullptr, nullptr};  // V-cycle iterate per precision
+  void* r[2] = {nullptr, nullptr};  // residual per precision (levels >= 2)
+};
+
+struct Problem {
+  int dim = 0, k = 0, L = 0;
+  unsigned flags = 0;
+  hipStream_t stream = nullptr;
+  std::vector<LevelBuffers> lv;  // index 0 unused, 1..L
+  double* c64_b = nullptr;       // FP64 coarse pair used by the FP32 V-cycle
+  double* c64_x = nullptr;
+  // CG state
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* sc = nullptr;       // scalar block (kScCount doubles)
+  double* partial = nullptr;  // 2 * reduction_parts() doubles
+  int* bad = nullptr;
+  double* host_sc = nullptr;  // pinned mirror of sc
+  int* host_bad = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  bool post_same_order = false;
+
+  ~Problem();
+  bool has(int prec) const;
+  const LevelGeom& geom(int level) const { return lv[level].g; }
+};
+
+// Message returned by vps_last_error() on the calling thread.
+void set_last_error(const std::string& msg);
+
+LevelGeom make_geom(int dim, int k, int level);
+long long level_nodes(int dim, int k, int level);
+size_t footprint_bytes(int dim, int degree, int L, unsigned flags);
+
+Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Problem** out);
+
+// Device steps (asynchronous on p->stream).
+Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x);
+Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x);
+Status coarse_solve(Problem* p, int prec, const void* b, void* x);
+Status vcycle(Problem* p, int prec, const void* b, void* x);
+
+struct SolveStats {
+  int iterations = 0;
+  double rel_residual = 0, true_rel_residual = 0;
+  int status = 0;
+};
+Status pcg(Problem* p, int mode, const double* b, double* x, double rtol, int maxit, SolveStats* st);
+
+// Stepwise CG (used by the server): same arithmetic as pcg(), one iteration per call.
+struct CgState {
+  int it = 0;
+  double bb = 0, rel = 1.0;
+  bool done = false;
+  SolveStats stats;
+};
+Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs);
+Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs);   // enqueue one iteration up to the norm copy
+Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync: decide, enqueue precond
+Status pcg_end(Problem* p, const double* b, double* x, CgState* cs);
+
+}  // namespace vps

@@ -1,0 +1,244 @@
+// Continuous-batching solve server (one GPU).
+//
+// Requests arrive with (dim, degree, level, rhs, tolerance, solve mode).  A
+// request is admitted, in arrival order, as soon as a slot is free and its
+// device footprint fits the remaining memory budget; idle hierarchies of
+// finished requests are cached per (dim, degree, level, mode) and handed to
+// later requests of the same shape, and evicted (least recently used first)
+// when a new shape needs their memory.  Every admitted request owns a HIP
+// stream, so the work of different requests overlaps on the device.  A tick
+// enqueues one CG iteration for every active request, waits for all of them,
+// then retires converged requests and enqueues the next preconditioner calls.
+// Each request runs exactly the arithmetic of a stand-alone vps_pcg_solve with
+// the same deterministic kernels, so its result does not depend on the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <deque>
+#include <list>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vps.h"
+#include "problem.hpp"
+
+namespace {
+
+struct Slot {
+  vps::Problem* prob = nullptr;
+  hipStream_t stream = nullptr;
+  size_t bytes = 0;
+  std::tuple<int, int, int, int> key;
+};
+
+struct Request {
+  long long id = 0;
+  int dim = 0, k = 0, level = 0, mode = 0, maxit = 0;
+  double rtol = 0;
+  const double* b = nullptr;
+  double* x = nullptr;
+  size_t bytes = 0;
+  Slot slot;
+  vps::CgState cs;
+  bool admitted = false, done = false;
+  vps_solve_stats_t stats{};
+};
+
+unsigned flags_for(int mode) {
+  return mode == VPS_SOLVE_MIXED ? VPS_FLAG_FP32_HIERARCHY : VPS_FLAG_FP64_HIERARCHY;
+}
+
+}  // namespace
+
+struct vps_server {
+  size_t budget = 0;
+  int max_active = 1;
+  long long next_id = 1;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;
+  std::map<long long, Request*> all;
+  std::list<Slot> idle;  // cached hierarchies, most recently used at the front
+  size_t in_use = 0, cached = 0;
+};
+
+namespace {
+
+int sfail(int code, const std::string& m) {
+  vps::set_last_error(m);
+  return code;
+}
+
+void free_slot(Slot& s) {
+  delete s.prob;
+  if (s.stream) hipStreamDestroy(s.stream);
+  s.prob = nullptr;
+  s.stream = nullptr;
+}
+
+// Try to give request r a hierarchy.  Returns 1 on success, 0 if it must wait, <0 on error.
+int acquire(vps_server* S, Request* r) {
+  auto key = std::make_tuple(r->dim, r->k, r->level, r->mode);
+  for (auto it = S->idle.begin(); it != S->idle.end(); ++it) {
+    if (it->key == key) {
+      r->slot = *it;
+      S->cached -= it->bytes;
+      S->in_use += it->bytes;
+      S->idle.erase(it);
+      return 1;
+    }
+  }
+  while (S->in_use + S->cached + r->bytes > S->budget && !S->idle.empty()) {
+    Slot victim = S->idle.back();
+    S->idle.pop_back();
+    S->cached -= victim.bytes;
+    free_slot(victim);
+  }
+  if (S->in_use + S->cached + r->bytes > S->budget) return 0;
+  Slot s;
+  s.key = key;
+  s.bytes = r->bytes;
+  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return sfail(VPS_EHIP, "hipStreamCreate failed");
+  }
+  vps::Status st = vps::create_problem(r->dim, r->k, r->level, flags_for(r->mode), s.stream, &s.prob);
+  if (st.code) {
+    hipStreamDestroy(s.stream);
+    return sfail(st.code, st.msg);
+  }
+  S->in_use += s.bytes;
+  r->slot = s;
+  return 1;
+}
+
+void release(vps_server* S, Request* r) {
+  S->in_use -= r->slot.bytes;
+  S->cached += r->slot.bytes;
+  S->idle.push_front(r->slot);
+  r->slot = Slot();
+}
+
+void finish(Request* r) {
+  r->done = true;
+  r->stats.iterations = r->cs.stats.iterations;
+  r->stats.rel_residual = r->cs.stats.rel_residual;
+  r->stats.true_rel_residual = r->cs.stats.true_rel_residual;
+  r->stats.status = r->cs.stats.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vps_server_create(size_t hbm_budget_bytes, int max_active, void* hip_stream, vps_server** out) {
+  (void)hip_stream;
+  if (!out || max_active < 1 || hbm_budget_bytes == 0) return sfail(VPS_EINVAL, "bad server arguments");
+  vps_server* s = new vps_server();
+  s->budget = hbm_budget_bytes;
+  s->max_active = max_active;
+  *out = s;
+  return VPS_OK;
+}
+
+int vps_server_submit(vps_server* s, int dim, int degree, int level, const double* b_dev, double* x_dev, double rtol,
+                      int solve_mode, int maxit, long long* ticket) {
+  if (!s || !b_dev || !x_dev || !ticket) return sfail(VPS_EINVAL, "null argument");
+  if (solve_mode != VPS_SOLVE_FP64 && solve_mode != VPS_SOLVE_MIXED) return sfail(VPS_EINVAL, "bad solve mode");
+  if (!(rtol > 0) || maxit < 1) return sfail(VPS_EINVAL, "rtol must be > 0 and maxit >= 1");
+  size_t bytes = 0;
+  if (int e = vps_footprint_bytes(dim, degree, level, flags_for(solve_mode), &bytes)) return sfail(e, vps_last_error());
+  if (bytes > s->budget) return sfail(VPS_EBUSY, "request footprint exceeds the server memory budget");
+  Request* r = new Request();
+  r->id = s->next_id++;
+  r->dim = dim;
+  r->k = degree;
+  r->level = level;
+  r->mode = solve_mode;
+  r->maxit = maxit;
+  r->rtol = rtol;
+  r->b = b_dev;
+  r->x = x_dev;
+  r->bytes = bytes;
+  s->queue.push_back(r);
+  s->all[r->id] = r;
+  *ticket = r->id;
+  return VPS_OK;
+}
+
+int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
+  if (!s) return sfail(VPS_EINVAL, "null server");
+  // admit in arrival order
+  while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+    Request* r = s->queue.front();
+    int got = acquire(s, r);
+    if (got < 0) return got;
+    if (got == 0) break;
+    s->queue.pop_front();
+    r->admitted = true;
+    vps::Status st = vps::pcg_begin(r->slot.prob, r->mode, r->b, r->x, &r->cs);
+    if (st.code) return sfail(st.code, st.msg);
+    if (r->cs.done) {
+      st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
+      if (st.code) return sfail(st.code, st.msg);
+      finish(r);
+      release(s, r);
+      continue;
+    }
+    s->active.push_back(r);
+  }
+  // one CG iteration for every active request, overlapped across streams
+  for (Request* r : s->active) {
+    vps::Status st = vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
+    if (st.code) return sfail(st.code, st.msg);
+  }
+  for (Request* r : s->active)
+    if (hipStreamSynchronize(r->slot.stream) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
+  std::vector<Request*> still;
+  for (Request* r : s->active) {
+    vps::Status st = vps::pcg_iterate_finish(r->slot.prob, r->mode, r->rtol, r->maxit, &r->cs);
+    if (st.code) return sfail(st.code, st.msg);
+    if (r->cs.done) {
+      st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
+      if (st.code) return sfail(st.code, st.msg);
+      finish(r);
+      release(s, r);
+    } else {
+      still.push_back(r);
+    }
+  }
+  s->active.swap(still);
+  if (n_active) *n_active = (int)s->active.size();
+  if (n_queued) *n_queued = (int)s->queue.size();
+  return VPS_OK;
+}
+
+int vps_server_poll(vps_server* s, long long ticket, int* done, vps_solve_stats_t* stats) {
+  if (!s || !done) return sfail(VPS_EINVAL, "null argument");
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return sfail(VPS_EINVAL, "unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  if (it->second->done && stats) *stats = it->second->stats;
+  return VPS_OK;
+}
+
+int vps_server_memory(vps_server* s, size_t* in_use, size_t* cached) {
+  if (!s) return sfail(VPS_EINVAL, "null server");
+  if (in_use) *in_use = s->in_use;
+  if (cached) *cached = s->cached;
+  return VPS_OK;
+}
+
+int vps_server_destroy(vps_server* s) {
+  if (!s) return VPS_OK;
+  for (Request* r : s->active)
+    if (r->slot.stream) hipStreamSynchronize(r->slot.stream);
+  for (Request* r : s->active) free_slot(r->slot);
+  for (Slot& sl : s->idle) free_slot(sl);
+  for (auto& kv : s->all) delete kv.second;
+  delete s;
+  return VPS_OK;
+}
+
+}  // extern "C"

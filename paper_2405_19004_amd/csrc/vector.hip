@@ -1,0 +1,198 @@
+// Vector operations of the outer CG and the V-cycle (Sec. 3: element-wise and
+// reduction-type vector operations).  Reductions are deterministic: a fixed
+// grid writes one partial per workgroup (fixed in-group tree order) and a
+// single workgroup sums the partials in a fixed order, so a result does not
+// depend on scheduling.  CG scalars live in device memory; only the residual
+// norm is copied to the host for the stopping test.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace vps {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ x, long long n, T v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+template <typename S, typename D>
+__global__ void cast_kernel(const S* __restrict__ src, D* __restrict__ dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+// dst = src with boundary entries 0 (FP64), also returns partials of src.src on the interior
+// and a non-finite flag.
+__global__ void copy_interior_kernel(const double* __restrict__ src, double* __restrict__ dst, int dim, long long n1d,
+                                     long long ntot, double* __restrict__ partial, int* __restrict__ bad) {
+  __shared__ double red[kRedThreads];
+  double acc = 0.0;
+  int nonfinite = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (long long)gridDim.x * blockDim.x) {
+    const long long i0 = i % n1d, r = i / n1d, i1 = r % n1d, i2 = r / n1d;
+    bool bnd = i0 == 0 || i0 == n1d - 1 || i1 == 0 || i1 == n1d - 1 || (dim == 3 && (i2 == 0 || i2 == n1d - 1));
+    double v = bnd ? 0.0 : src[i];
+    if (!isfinite(v)) nonfinite = 1;
+    dst[i] = v;
+    acc = fma(v, v, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (nonfinite) atomicOr(bad, 1);
+}
+
+__device__ __forceinline__ void block_reduce2(double a, double b, double* out_a, double* out_b) {
+  __shared__ double ra[kRedThreads], rb[kRedThreads];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      ra[threadIdx.x] += ra[threadIdx.x + s];
+      rb[threadIdx.x] += rb[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *out_a = ra[0];
+    *out_b = rb[0];
+  }
+}
+
+// partials of a.b (slot 0) and c.d (slot 1); c may be null
+__global__ void dot2_kernel(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                            const double* __restrict__ d, long long n, double* __restrict__ partial) {
+  double s0 = 0.0, s1 = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    s0 = fma(a[i], b[i], s0);
+    if (c) s1 = fma(c[i], d[i], s1);
+  }
+  block_reduce2(s0, s1, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
+}
+
+// Sum 2*nparts partials (pairs) into out[0], out[1] in a fixed order.
+__global__ void finalize2_kernel(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    s0 += partial[2 * i];
+    s1 += partial[2 * i + 1];
+  }
+  block_reduce2(s0, s1, &out[0], &out[1]);
+}
+
+__global__ void finalize1_kernel(const double* __restrict__ partial, int nparts, double* __restrict__ out) {
+  double s0 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s0 += partial[i];
+  double dummy;
+  block_reduce2(s0, 0.0, &out[0], &dummy);
+}
+
+// CG step: x += alpha p, r -= alpha q, with alpha = s[RZ] / s[PQ];
+// partials of r.r (slot 0) and r.z (slot 1, z = the previous preconditioned residual).
+__global__ void cg_update_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                                 const double* __restrict__ q, const double* __restrict__ z, long long n,
+                                 const double* __restrict__ sc, double* __restrict__ partial) {
+  const double alpha = sc[kScRZ] / sc[kScPQ];
+  double s0 = 0.0, s1 = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    s0 = fma(ri, ri, s0);
+    s1 = fma(ri, z[i], s1);
+  }
+  block_reduce2(s0, s1, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
+}
+
+// p = z + beta p, beta from the scalar block
+__global__ void cg_direction_kernel(double* __restrict__ p, const double* __restrict__ z, long long n,
+                                    const double* __restrict__ sc) {
+  const double beta = sc[kScBeta];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
+// beta = (rz_new - flexible * r_new.z_old) / rz ; rz <- rz_new.  Also flags non-finite values.
+__global__ void cg_beta_kernel(double* __restrict__ sc, int flexible) {
+  const double rz_new = sc[kScRZNew];
+  const double num = flexible ? rz_new - sc[kScRZOld] : rz_new;
+  sc[kScBeta] = num / sc[kScRZ];
+  sc[kScRZ] = rz_new;
+}
+
+}  // namespace
+
+static unsigned grid_for(long long n) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+int reduction_parts() { return 1024; }
+
+hipError_t launch_fill(int prec, void* x, long long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, (double*)x, n, v);
+  else
+    hipLaunchKernelGGL(fill_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, (float*)x, n, (float)v);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(int from_prec, const void* src, void* dst, long long n, hipStream_t st) {
+  if (from_prec == 0)
+    hipLaunchKernelGGL((cast_kernel<double, float>), dim3(grid_for(n)), dim3(256), 0, st, (const double*)src,
+                       (float*)dst, n);
+  else
+    hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, st, (const float*)src,
+                       (double*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, double* dst, double* partial,
+                                     double* out, int* bad, hipStream_t st) {
+  long long ntot = dim == 2 ? n1d * n1d : n1d * n1d * n1d;
+  const int parts = reduction_parts();
+  hipLaunchKernelGGL(copy_interior_kernel, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot, partial,
+                     bad);
+  hipLaunchKernelGGL(finalize1_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, long long n,
+                       double* partial, double* out, hipStream_t st) {
+  const int parts = reduction_parts();
+  hipLaunchKernelGGL(dot2_kernel, dim3(parts), dim3(kRedThreads), 0, st, a, b, c, d, n, partial);
+  hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
+                            double* sc, double* partial, hipStream_t st) {
+  const int parts = reduction_parts();
+  hipLaunchKernelGGL(cg_update_kernel, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z, n, sc, partial);
+  hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, sc + kScRR);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st) {
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(1), 0, st, sc, flexible);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(double* p, const double* z, long long n, const double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, z, n, sc);
+  return hipGetLastError();
+}
+
+}  // namespace vps
