@@ -45,6 +45,14 @@ def colour_pass_bytes(d, k, es):
     return es * (n ** d + 2 * m ** d)
 
 
+def smoother_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("smoother.hip", "device_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2405_19004_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +61,10 @@ def parse():
     ap.add_argument("--serve", type=int, default=120, help="requests in the serving run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only 8 FP32 and 8 FP64 colour passes on the finest level, twice (for counter runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only a plain device copy of this many MiB, 4 times (counter calibration)")
     return ap.parse_args()
 
 
@@ -176,7 +188,26 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.copy_mib:
+        src = torch.ones(a.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 4}))
+        return
     P = v.Problem(D, K, L, v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY)
+    if a.kernels_only:
+        kap, co = synth.fourier_modes(D, seed=1)
+        for dt_ in (torch.float32, torch.float64):
+            bb = P.rhs_sine_modes(kap, co, dtype=dt_)
+            xx = torch.zeros_like(bb)
+            for _ in range(2):
+                for c in range(8):
+                    P.color_pass(bb, xx, c)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "patches_per_colour": list(P.info().color_count)}))
+        return
     N = P.n()
     kap, co = synth.fourier_modes(D, seed=1)
     b = P.rhs_sine_modes(kap, co)
@@ -244,7 +275,9 @@ def main():
     traffic = None
     tf = os.path.join(ROOT, "profiles", "colour_pass_3d_q4_fp32_traffic.json")
     if os.path.exists(tf):
-        traffic = json.load(open(tf)).get("bytes_per_launch")
+        rec = json.load(open(tf))
+        if rec.get("source_hash") == smoother_source_hash():  # counters describe this exact kernel source
+            traffic = rec.get("bytes_per_launch")
     out["roofline"] = {"bound": "alu", "achieved": flops / t_all / 1e12, "peak": PEAK_FP32 / 1e12,
                        "unit": "TFLOP/s", "frac": flops / t_all / PEAK_FP32, "traffic": traffic,
                        "kernel": "colour_pass_kernel<3,4,float,false>", "avg_launch_us": 1e6 * t_all,

@@ -1,0 +1,104 @@
+"""Serving (continuous batching) on the GPU: results alone == in the mix, admission by memory budget."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_19004_amd as vps  # noqa: E402
+
+SHAPES = [(2, 1, 7), (3, 2, 3), (2, 7, 4), (3, 4, 3), (2, 3, 6), (3, 1, 5), (3, 6, 2), (2, 5, 5)]
+
+
+def _rhs(d, k, L, seed):
+    P = vps.Problem(d, k, L, vps.VPS_FLAG_FP32_HIERARCHY | vps.VPS_FLAG_NO_SOLVER)
+    kap, co = synth.fourier_modes(d, seed=seed)
+    b = P.rhs_sine_modes(kap, co)
+    P.close()
+    return b
+
+
+def _alone(d, k, L, b, mode):
+    P = vps.Problem(d, k, L)
+    x, st = P.pcg_solve(b, rtol=1e-8, mode=mode)
+    torch.cuda.synchronize()
+    out = x.clone(), st.iterations, st.status
+    P.close()
+    return out
+
+
+def _serve(reqs, budget, max_active, mode):
+    srv = vps.vps_server_create(budget, max_active)
+    xs, tickets = [], []
+    peak = 0
+    try:
+        for (d, k, L), b in reqs:
+            x = torch.full_like(b, 5.0)
+            xs.append(x)
+            tickets.append(vps.vps_server_submit(srv, d, k, L, b.data_ptr(), x.data_ptr(), 1e-8, mode, 50))
+        for _ in range(10000):
+            active, queued = vps.vps_server_step(srv)
+            in_use, cached = vps.vps_server_memory(srv)
+            peak = max(peak, in_use + cached)
+            if active == 0 and queued == 0:
+                break
+        stats = [vps.vps_server_poll(srv, t) for t in tickets]
+    finally:
+        vps.vps_server_destroy(srv)
+    return xs, stats, peak
+
+
+@pytest.mark.parametrize("mode", [vps.VPS_SOLVE_MIXED, vps.VPS_SOLVE_FP64])
+def test_results_identical_alone_and_in_the_mix(mode):
+    reqs = [((d, k, L), _rhs(d, k, L, 100 + i)) for i, (d, k, L) in enumerate(SHAPES)]
+    reqs += reqs[:3]  # repeated shapes reuse cached hierarchies
+    xs, stats, _ = _serve(reqs, 8 << 30, 4, mode)
+    for ((d, k, L), b), x, (done, st) in zip(reqs, xs, stats):
+        print("request", d, k, L, st.iterations, st.status, flush=True)
+        assert done and st.status == 0
+        ref, its, status = _alone(d, k, L, b, mode)
+        assert status == 0 and its == st.iterations
+        assert torch.equal(x, ref)  # deterministic kernels: bitwise identical
+        bh = b.cpu().numpy()
+        r = bh - mesh.apply_operator(d, k, L, x.cpu().numpy())
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(bh)
+
+
+def test_admission_respects_a_tight_budget():
+    reqs = [((3, 2, 4), _rhs(3, 2, 4, 7)), ((3, 3, 4), _rhs(3, 3, 4, 8)), ((2, 4, 6), _rhs(2, 4, 6, 9))]
+    need = max(vps.vps_footprint_bytes(d, k, L, vps.VPS_FLAG_FP32_HIERARCHY) for (d, k, L), _ in reqs)
+    budget = int(need * 1.2)  # room for one request at a time
+    xs, stats, peak = _serve(reqs, budget, 8, vps.VPS_SOLVE_MIXED)
+    assert peak <= budget
+    for (done, st) in stats:
+        assert done and st.status == 0
+
+
+def test_bad_requests_fail_alone():
+    b_ok = _rhs(2, 2, 4, 11)
+    b_nan = b_ok.clone()
+    b_nan[300] = float("nan")
+    srv = vps.vps_server_create(1 << 30, 4)
+    try:
+        with pytest.raises(vps.VpsError) as e:
+            vps.vps_server_submit(srv, 3, 7, 8, b_ok.data_ptr(), b_ok.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        assert e.value.status == vps.VPS_EBUSY
+        x1, x2 = torch.zeros_like(b_ok), torch.zeros_like(b_ok)
+        t1 = vps.vps_server_submit(srv, 2, 2, 4, b_nan.data_ptr(), x1.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        t2 = vps.vps_server_submit(srv, 2, 2, 4, b_ok.data_ptr(), x2.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        for _ in range(100):
+            a, q = vps.vps_server_step(srv)
+            if a == 0 and q == 0:
+                break
+        d1, s1 = vps.vps_server_poll(srv, t1)
+        d2, s2 = vps.vps_server_poll(srv, t2)
+        assert d1 and s1.status == vps.VPS_ENOTFINITE
+        assert d2 and s2.status == 0
+    finally:
+        vps.vps_server_destroy(srv)
