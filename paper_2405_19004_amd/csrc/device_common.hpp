@@ -22,6 +22,8 @@ struct DevTables {
   T Ab[kMaxDegree * kMaxN];  // assembled-stiffness band rows
   T P[kMaxN * (kMaxDegree + 1)];          // prolongation (2k+1) x (k+1)
   T Rb[kMaxDegree * (4 * kMaxDegree + 1)];  // restriction band rows k x (4k+1)
+  T inv3[kMaxM * kMaxM * kMaxM];  // 1 / (lam[a2] + lam[a1] + lam[a0]), index (a2*m + a1)*m + a0
+  T inv2[kMaxM * kMaxM];          // 1 / (lam[a1] + lam[a0]),           index a1*m + a0
 };
 
 template <typename T>
@@ -34,6 +36,11 @@ inline void fill_dev_tables(int k, DevTables<T>& out) {
   for (int i = 0; i < k * n; ++i) { out.Mb[i] = (T)t.Mband[i]; out.Ab[i] = (T)t.Aband[i]; }
   for (int i = 0; i < n * np; ++i) out.P[i] = (T)t.P[i];
   for (int i = 0; i < k * (4 * k + 1); ++i) out.Rb[i] = (T)t.Rband[i];
+  for (int a2 = 0; a2 < m; ++a2)
+    for (int a1 = 0; a1 < m; ++a1) {
+      out.inv2[a2 * m + a1] = (T)(1.0 / (t.lam[a2] + t.lam[a1]));
+      for (int a0 = 0; a0 < m; ++a0) out.inv3[(a2 * m + a1) * m + a0] = (T)(1.0 / (t.lam[a2] + t.lam[a1] + t.lam[a0]));
+    }
 }
 
 // Geometry of one level as the kernels see it.

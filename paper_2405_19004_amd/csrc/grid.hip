@@ -41,6 +41,39 @@ __device__ __forceinline__ const DevTables<float>& gtab<float>(int k) { return g
 
 __device__ __forceinline__ bool is_bnd(long long i, long long n1d) { return i <= 0 || i >= n1d - 1; }
 
+// Tables re-derived through an opaque wave-uniform zero inside each task loop, so
+// the compiler does not hoist every table entry out of the loop into SGPRs (and spill).
+template <typename T>
+__device__ __forceinline__ const DevTables<T>& gtab_fresh(int k) {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return *reinterpret_cast<const DevTables<T>*>(reinterpret_cast<const char*>(&gtab<T>(k)) + z);
+}
+
+// Load n values of one row, positions g0 .. g0+n-1, as zero outside the interior (1 .. n1d-2).
+// `interior` (wave-uniform) says the whole range is interior: then the loads are unconditional.
+template <typename T, int N>
+__device__ __forceinline__ void load_row(T (&in)[N], const T* __restrict__ row, long long g0, long long n1d,
+                                         bool interior, bool row_ok) {
+  if (interior) {
+    const T* p = row + g0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) in[j] = p[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const long long g = g0 + j;
+      const long long gc = g < 0 ? 0 : (g > n1d - 1 ? n1d - 1 : g);
+      const T v = row[gc];
+      in[j] = (g <= 0 || g >= n1d - 1) ? T(0) : v;
+    }
+  }
+  if (!row_ok) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) in[j] = T(0);
+  }
+}
+
 // ----------------------------------------------------------------- operator
 
 // Cells per tile along (x0, x1, x2).
@@ -60,7 +93,6 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   constexpr int NT = S::NT, W = 2 * K + 1;
   constexpr int TO0 = K * S::C0, TO1 = K * S::C1, TO2 = K * S::C2;
   constexpr int TI0 = TO0 + K + 1, TI1 = TO1 + K + 1, TI2 = D == 3 ? TO2 + K + 1 : 1;
-  const DevTables<T>& tb = gtab<T>(K);
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = blk % tiles0;
   const int ty = (blk / tiles0) % tiles1;
@@ -73,17 +105,15 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   __shared__ T PA[TI2 * TI1 * TO0];
 
   // stage x0: rows (z, y) of the input block
+  const bool xin = o0 - K >= 1 && o0 - K + TI0 - 1 <= n1d - 2;
   for (int task = tid; task < TI2 * TI1; task += NT) {
+    const DevTables<T>& tb = gtab_fresh<T>(K);
     const int zl = task / TI1, yl = task - zl * TI1;
     const long long gz = D == 3 ? o2 - K + zl : 0, gy = o1 - K + yl;
     T in[TI0];
     const bool row_ok = !is_bnd(gy, n1d) && (D == 2 || !is_bnd(gz, n1d));
-    const long long rb = (D == 3 ? gz * n1d2 : 0) + gy * n1d;
-#pragma unroll
-    for (int j = 0; j < TI0; ++j) {
-      const long long gx = o0 - K + j;
-      in[j] = (row_ok && !is_bnd(gx, n1d)) ? x[rb + gx] : T(0);
-    }
+    const long long gzc = gz < 0 ? 0 : (gz > n1d - 1 ? n1d - 1 : gz), gyc = gy < 0 ? 0 : (gy > n1d - 1 ? n1d - 1 : gy);
+    load_row<T, TI0>(in, x + (D == 3 ? gzc * n1d2 : 0) + gyc * n1d, o0 - K, n1d, xin, row_ok);
 #pragma unroll
     for (int xo = 0; xo < TO0; ++xo) {
       const int c = xo % K;
@@ -103,6 +133,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   if constexpr (D == 2) {
     // stage x1: columns xo, outputs y = A1 (M1 x) + M1 (A1 x)
     for (int task = tid; task < TO0; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int xo = task;
       T pm[TI1], pa[TI1];
 #pragma unroll
@@ -133,6 +164,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
     __shared__ T V[TI2 * TO1 * TO0];
     // stage x1: columns (z, xo)
     for (int task = tid; task < TI2 * TO0; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int zl = task / TO0, xo = task - zl * TO0;
       T pm[TI1], pa[TI1];
 #pragma unroll
@@ -158,6 +190,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
     __syncthreads();
     // stage x2: columns (yo, xo); y = A1 U + M1 V
     for (int task = tid; task < TO1 * TO0; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int yo = task / TO0, xo = task - yo * TO0;
       T u[TI2], v[TI2];
 #pragma unroll
@@ -204,7 +237,6 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   constexpr int C = ProShape<D, K>::C, NT = ProShape<D, K>::NT;
   constexpr int TI = K * C + 1, TO = 2 * K * C, TIz = D == 3 ? TI : 1;
   constexpr int NP = K + 1;
-  const DevTables<T>& tb = gtab<T>(K);
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
   const long long c0 = (long long)tx * K * C, c1 = (long long)ty * K * C, c2 = (long long)tz * K * C;
@@ -214,6 +246,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   __shared__ T T1[TIz * TI * TO];
   // stage x0: coarse rows
   for (int task = tid; task < TIz * TI; task += NT) {
+    const DevTables<T>& tb = gtab_fresh<T>(K);
     const int zl = task / TI, yl = task - zl * TI;
     const long long gz = D == 3 ? c2 + zl : 0, gy = c1 + yl;
     const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && (D == 2 || (gz < n1dc && !is_bnd(gz, n1dc)));
@@ -238,6 +271,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   __syncthreads();
   if constexpr (D == 2) {
     for (int task = tid; task < TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int xo = task;
       T in[TI];
 #pragma unroll
@@ -259,6 +293,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   } else {
     __shared__ T T2[TI * TO * TO];
     for (int task = tid; task < TI * TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int zl = task / TO, xo = task - zl * TO;
       T in[TI];
 #pragma unroll
@@ -277,6 +312,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
     }
     __syncthreads();
     for (int task = tid; task < TO * TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int yo = task / TO, xo = task - yo * TO;
       T in[TI];
 #pragma unroll
@@ -314,7 +350,6 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
                                                                            long long n1dc, long long n1df, int tiles) {
   constexpr int C = ResShape<D, K>::C, NT = ResShape<D, K>::NT;
   constexpr int TO = K * C, TI = 2 * K * C + 2 * K + 1, TIz = D == 3 ? TI : 1, RW = 4 * K + 1;
-  const DevTables<T>& tb = gtab<T>(K);
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
   const long long c0 = (long long)tx * TO, c1 = (long long)ty * TO, c2 = (long long)tz * TO;
@@ -323,15 +358,14 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
   __shared__ T T1[TIz * TI * TO];
   for (int task = tid; task < TIz * TI; task += NT) {
+    const DevTables<T>& tb = gtab_fresh<T>(K);
     const int zl = task / TI, yl = task - zl * TI;
     const long long gz = D == 3 ? f2 + zl : 0, gy = f1 + yl;
     const bool ok = !is_bnd(gy, n1df) && (D == 2 || !is_bnd(gz, n1df));
     T in[TI];
-#pragma unroll
-    for (int j = 0; j < TI; ++j) {
-      const long long gx = f0 + j;
-      in[j] = (ok && !is_bnd(gx, n1df)) ? rf[(D == 3 ? gz * nf2 : 0) + gy * n1df + gx] : T(0);
-    }
+    const long long gzc = gz < 0 ? 0 : (gz > n1df - 1 ? n1df - 1 : gz), gyc = gy < 0 ? 0 : (gy > n1df - 1 ? n1df - 1 : gy);
+    const bool xin = f0 >= 1 && f0 + TI - 1 <= n1df - 2;
+    load_row<T, TI>(in, rf + (D == 3 ? gzc * nf2 : 0) + gyc * n1df, f0, n1df, xin, ok);
 #pragma unroll
     for (int xo = 0; xo < TO; ++xo) {
       const int a = xo % K, cc = xo / K;
@@ -347,6 +381,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   __syncthreads();
   if constexpr (D == 2) {
     for (int task = tid; task < TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int xo = task;
       T in[TI];
 #pragma unroll
@@ -368,6 +403,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   } else {
     __shared__ T T2[TI * TO * TO];
     for (int task = tid; task < TI * TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int zl = task / TO, xo = task - zl * TO;
       T in[TI];
 #pragma unroll
@@ -386,6 +422,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
     }
     __syncthreads();
     for (int task = tid; task < TO * TO; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
       const int yo = task / TO, xo = task - yo * TO;
       T in[TI];
 #pragma unroll

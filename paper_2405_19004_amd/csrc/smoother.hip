@@ -66,7 +66,15 @@ struct SmootherLds {
   static constexpr int offB = D == 3 ? A3 : A2;
 };
 
-__device__ __forceinline__ bool on_boundary(long long i, long long n1d) { return i == 0 || i == n1d - 1; }
+// The constant tables re-derived through an opaque (but wave-uniform) zero
+// offset: keeps the compiler from hoisting every table load out of a stage's
+// task loop, which would pin more values in SGPRs than exist and spill them.
+template <typename T>
+__device__ __forceinline__ const DevTables<T>& tab_fresh(int k) {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return *reinterpret_cast<const DevTables<T>*>(reinterpret_cast<const char*>(&tab<T>(k)) + z);
+}
 
 template <int D, int K, typename T, bool ADD>
 __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
@@ -76,10 +84,10 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
   constexpr int PPW = SmootherShape<D, K>::PPW, NT = SmootherShape<D, K>::NT;
   using L = SmootherLds<D, K, T, ADD>;
   constexpr int RS = L::RS;
+  constexpr int RW = 2 * K * PPW;  // interior row segment incl. the shared-face gaps
   __shared__ T smem[L::total];
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
-  const DevTables<T>& tb = tab<T>(K);
 
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int g0 = blk % groups0;
@@ -93,55 +101,115 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
   const long long s2 = D == 3 ? (long long)K * (p2 + 2 * t2) : 0;
   const long long n1d2 = n1d * n1d;
   const int tid = threadIdx.x;
-  const int seg = 2 * K * P + 1;  // valid length of the row segment
+  const int seg = 2 * K * P + 1;  // valid length of the closure row segment
+
+  // rows of the patch-interior block handled by stage "b" (residual/Sᵀ along the slowest axis):
+  // task = (i1, q, i0) in 3D, (q, i0) in 2D; prefetch b there before anything else.
+  constexpr int NB = D == 3 ? PPW * m * m : PPW * m;
+  constexpr int RB = (NB + NT - 1) / NT;
+  // Offsets inside one workgroup's block fit in 32 bits (checked by the launcher).
+  const int ld1 = (int)n1d, ld2 = D == 3 ? (int)n1d2 : 0;
+  const long long origin = (D == 3 ? s2 * n1d2 : 0) + s1 * n1d + s0;  // closure corner of the first patch
+  T* xo = x + origin;  // same restrict object as x: closure loads, x^I loads and stores
+  const T* bo = b + origin;
+  T bpre[RB][m];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const int task = rr * NT + tid;
+    int q, i0, i1;
+    if constexpr (D == 3) {
+      i1 = task / (PPW * m);
+      const int r = task - i1 * (PPW * m);
+      q = r / m;
+      i0 = r - q * m;
+    } else {
+      q = task / m;
+      i0 = task - q * m;
+      i1 = 0;
+    }
+    // clamp to a valid patch-interior position: the loads are then always in bounds and the
+    // values of inactive tasks are simply never used
+    q = min(q, P - 1);
+    if constexpr (D == 3) i1 = min(i1, m - 1);
+    const int off = (D == 3 ? ld2 + (1 + i1) * ld1 : ld1) + 2 * K * q + 1 + i0;
+    const int st = D == 3 ? ld2 : ld1;
+#pragma unroll
+    for (int i = 0; i < m; ++i) bpre[rr][i] = bo[off + i * st];
+  }
+
+  // ---- closure segment -> LDS.  Work item = (column c, row j1 in 3D); the slowest axis is
+  // walked in an unrolled loop, so an address costs one add and the Dirichlet tests on that
+  // axis are compile-time.  Every closure node lies inside the grid: loads are unconditional
+  // and Dirichlet nodes are replaced by 0 afterwards (boundary entries of x are ignored).
+  if constexpr (!ADD) {
+    T* X = bufB;
+    constexpr int NW = D == 3 ? RS * n : RS;
+    const bool lo1 = s1 == 0, hi1 = s1 + n - 1 == n1d - 1;
+    const bool lo2 = D == 3 && s2 == 0, hi2 = D == 3 && s2 + n - 1 == n1d - 1;
+    for (int w = tid; w < NW; w += NT) {
+      const int c = w % RS, j1 = D == 3 ? w / RS : 0;
+      const int cl = min(c, seg - 1);
+      const long long gc = s0 + cl;
+      bool bad = gc == 0 || gc == n1d - 1;
+      if constexpr (D == 3) bad = bad || (j1 == 0 && lo1) || (j1 == n - 1 && hi1);
+      const int base = (D == 3 ? j1 * ld1 : 0) + cl;
+      constexpr int NS = n;  // slow-axis length (j2 in 3D, j1 in 2D)
+      const int sstride = D == 3 ? ld2 : ld1;
+      T v[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) v[j] = xo[base + j * sstride];
+      const bool lo = D == 3 ? lo2 : lo1, hi = D == 3 ? hi2 : hi1;
+      if (c < seg) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          const bool zero = bad || (j == 0 && lo) || (j == NS - 1 && hi);
+          X[(D == 3 ? j * n + j1 : j) * RS + c] = zero ? T(0) : v[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
 
   if constexpr (D == 3) {
     T* U = bufB;  // [q][j2][i1][i0]
     T* V = bufB + PPW * n * m * m;
     if constexpr (!ADD) {
-      // ---- stage 1: closure of all PPW patches -> LDS (rows of the segment, coalesced)
-      T* X = bufB;
-      for (int idx = tid; idx < n * n * RS; idx += NT) {
-        const int r = idx / RS, c = idx - r * RS;
-        if (c < seg) {
-          const int j2 = r / n, j1 = r - j2 * n;
-          const long long g2 = s2 + j2, g1 = s1 + j1, g0n = s0 + c;
-          T v = T(0);
-          if (!on_boundary(g2, n1d) && !on_boundary(g1, n1d) && !on_boundary(g0n, n1d))
-            v = x[g2 * n1d2 + g1 * n1d + g0n];
-          X[idx] = v;
-        }
-      }
-      __syncthreads();
-      // ---- stage 2: contract x0 with Mc and Ac: lines (q, j2, j1) of n values
+      const T* X = bufB;
       T* PM = bufA;
       T* PA = bufA + PPW * n * n * m;
-      for (int task = tid; task < PPW * n * n; task += NT) {
+      // ---- contract x0 with Mc and Ac: lines (q, j2, j1) of n values
+      for (int base = 0; base < PPW * n * n; base += NT) {
+        const int task = base + tid;
         const int q = task / (n * n), r = task - q * (n * n);
-        if (q < P) {
+        if (task < PPW * n * n && q < P) {
+          const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[r * RS + 2 * K * q + j];
 #pragma unroll
           for (int i = 0; i < m; ++i) {
-            T sm = T(0), sa = T(0);
+            T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) {
-              sm = fma(tb.Mc[i * n + j], in[j], sm);
-              sa = fma(tb.Ac[i * n + j], in[j], sa);
-            }
+            for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
             PM[(q * n * n + r) * m + i] = sm;
+          }
+#pragma unroll
+          for (int i = 0; i < m; ++i) {
+            T sa = T(0);
+#pragma unroll
+            for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
             PA[(q * n * n + r) * m + i] = sa;
           }
         }
       }
       __syncthreads();
-      // ---- stage 3: contract x1: lines (q, j2, i0) along j1.
-      //      U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)   (partial products reused)
-      for (int task = tid; task < PPW * n * m; task += NT) {
+      // ---- contract x1: lines (q, j2, i0) along j1; U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)
+      for (int base = 0; base < PPW * n * m; base += NT) {
+        const int task = base + tid;
         const int q = task / (n * m), r = task - q * (n * m);
         const int j2 = r / m, i0 = r - j2 * m;
-        if (q < P) {
+        if (task < PPW * n * m && q < P) {
+          const DevTables<T>& tb = tab_fresh<T>(K);
           T pm[n], pa[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
@@ -164,17 +232,19 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
       __syncthreads();
     }
-    // ---- stage 4: contract x2 (residual) and apply S^T along x2: lines (q, i1, i0)
+    // ---- contract x2 (residual) and apply Sᵀ along x2: lines (i1, q, i0)
     T* W = bufA;  // [q][a2][i1][i0]
-    for (int task = tid; task < PPW * m * m; task += NT) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
       const int i1 = task / (PPW * m), r = task - i1 * (PPW * m);
       const int q = r / m, i0 = r - q * m;
-      if (q < P) {
-        const long long gb = (s2 + 1) * n1d2 + (s1 + 1 + i1) * n1d + (s0 + 2 * K * q + 1 + i0);
+      if (task < NB && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T res[m];
         if constexpr (ADD) {
 #pragma unroll
-          for (int i = 0; i < m; ++i) res[i] = b[gb + i * n1d2];
+          for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
         } else {
           T u[n], v[n];
 #pragma unroll
@@ -190,7 +260,7 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
               s = fma(tb.Ac[i * n + j], u[j], s);
               s = fma(tb.Mc[i * n + j], v[j], s);
             }
-            res[i] = b[gb + i * n1d2] - res_scale * s;
+            res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
 #pragma unroll
@@ -203,12 +273,14 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
     }
     __syncthreads();
-    // ---- stage 5: S^T along x1: lines (q, a2, i0)
+    // ---- Sᵀ along x1: lines (q, a2, i0)
     T* W2 = bufB;
-    for (int task = tid; task < PPW * m * m; task += NT) {
+    for (int base = 0; base < PPW * m * m; base += NT) {
+      const int task = base + tid;
       const int q = task / (m * m), r = task - q * (m * m);
       const int a2 = r / m, i0 = r - a2 * m;
-      if (q < P) {
+      if (task < PPW * m * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W[((q * m + a2) * m + i) * m + i0];
@@ -222,38 +294,40 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
     }
     __syncthreads();
-    // ---- stage 6: S^T along x0, divide by the eigenvalue sums, S along x0: lines (q, a2, a1)
-    for (int task = tid; task < PPW * m * m; task += NT) {
+    // ---- Sᵀ along x0, scale by 1/(lam2+lam1+lam0), S along x0: lines (q, a2, a1)
+    for (int base = 0; base < PPW * m * m; base += NT) {
+      const int task = base + tid;
       const int q = task / (m * m), r = task - q * (m * m);
-      const int a2 = r / m, a1 = r - a2 * m;
-      if (q < P) {
+      if (task < PPW * m * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m], z[m];
-        const int base = ((q * m + a2) * m + a1) * m;
+        const int basei = (q * m * m + r) * m;
 #pragma unroll
-        for (int i = 0; i < m; ++i) in[i] = W2[base + i];
-        const T l21 = tb.lam[a2] + tb.lam[a1];
+        for (int i = 0; i < m; ++i) in[i] = W2[basei + i];
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
-          z[a] = s / (l21 + tb.lam[a]);
+          z[a] = s * tb.inv3[r * m + a];
         }
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
-          W[base + i] = s;
+          W[basei + i] = s;
         }
       }
     }
     __syncthreads();
-    // ---- stage 7: S along x1: lines (q, a2, i0)
-    for (int task = tid; task < PPW * m * m; task += NT) {
+    // ---- S along x1: lines (q, a2, i0)
+    for (int base = 0; base < PPW * m * m; base += NT) {
+      const int task = base + tid;
       const int q = task / (m * m), r = task - q * (m * m);
       const int a2 = r / m, i0 = r - a2 * m;
-      if (q < P) {
+      if (task < PPW * m * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W[((q * m + a2) * m + a) * m + i0];
@@ -267,11 +341,13 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
     }
     __syncthreads();
-    // ---- stage 8: S along x2: lines (q, i1, i0); correction -> LDS [q][i2][i1][i0]
-    for (int task = tid; task < PPW * m * m; task += NT) {
+    // ---- S along x2: lines (q, i1, i0); correction -> LDS [q][i2][i1][i0]
+    for (int base = 0; base < PPW * m * m; base += NT) {
+      const int task = base + tid;
       const int q = task / (m * m), r = task - q * (m * m);
       const int i1 = r / m, i0 = r - i1 * m;
-      if (q < P) {
+      if (task < PPW * m * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W2[((q * m + a) * m + i1) * m + i0];
@@ -285,67 +361,74 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
     }
     __syncthreads();
-    // ---- stage 9: x^I += correction, rows of the segment (coalesced)
-    constexpr int RW = 2 * K * PPW;
-    for (int idx = tid; idx < m * m * RW; idx += NT) {
-      const int r = idx / RW, c = idx - r * RW;
+    // ---- x^I += correction.  Work item = (column c, row i1); i2 walked unrolled; reads
+    //      issued before writes.
+    for (int w = tid; w < RW * m; w += NT) {
+      const int c = w % RW, i1 = w / RW;
       const int q = c / (2 * K), i0 = c - q * (2 * K);
       if (q < P && i0 < m) {
-        const int i2 = r / m, i1 = r - i2 * m;
-        const long long g = (s2 + 1 + i2) * n1d2 + (s1 + 1 + i1) * n1d + (s0 + 1 + c);
-        x[g] += W[((q * m + i2) * m + i1) * m + i0];
+        const int base = ld2 + (1 + i1) * ld1 + 1 + c;
+        T old[m];
+#pragma unroll
+        for (int i2 = 0; i2 < m; ++i2) old[i2] = xo[base + i2 * ld2];
+#pragma unroll
+        for (int i2 = 0; i2 < m; ++i2) xo[base + i2 * ld2] = old[i2] + W[((q * m + i2) * m + i1) * m + i0];
       }
     }
   } else {
     // ================================ 2D =====================================
     T* W = bufB;  // [q][a1][i0]
     if constexpr (!ADD) {
-      // ---- stage 1: closure segment -> LDS
-      T* X = bufB;
-      for (int idx = tid; idx < n * RS; idx += NT) {
-        const int j1 = idx / RS, c = idx - j1 * RS;
-        if (c < seg) {
-          const long long g1 = s1 + j1, g0n = s0 + c;
-          T v = T(0);
-          if (!on_boundary(g1, n1d) && !on_boundary(g0n, n1d)) v = x[g1 * n1d + g0n];
-          X[idx] = v;
-        }
-      }
-      __syncthreads();
-      // ---- stage 2: contract x0 with Mc and Ac: lines (q, j1)
+      const T* X = bufB;
       T* PM = bufA;
       T* PA = bufA + PPW * n * m;
-      for (int task = tid; task < PPW * n; task += NT) {
+      // ---- contract x0 with Mc and Ac: lines (q, j1)
+      for (int base = 0; base < PPW * n; base += NT) {
+        const int task = base + tid;
         const int q = task / n, j1 = task - q * n;
-        if (q < P) {
+        if (task < PPW * n && q < P) {
+          const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[j1 * RS + 2 * K * q + j];
 #pragma unroll
           for (int i = 0; i < m; ++i) {
-            T sm = T(0), sa = T(0);
+            T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) {
-              sm = fma(tb.Mc[i * n + j], in[j], sm);
-              sa = fma(tb.Ac[i * n + j], in[j], sa);
-            }
+            for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
             PM[(q * n + j1) * m + i] = sm;
+          }
+#pragma unroll
+          for (int i = 0; i < m; ++i) {
+            T sa = T(0);
+#pragma unroll
+            for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
             PA[(q * n + j1) * m + i] = sa;
           }
         }
       }
       __syncthreads();
-      // ---- stage 3: residual along x1, r = b - (A1 (M0 x) + M1 (A0 x)), then S^T along x1
-      for (int task = tid; task < PPW * m; task += NT) {
-        const int q = task / m, i0 = task - q * m;
-        if (q < P) {
-          T pm[n], pa[n], res[m];
+    }
+    // ---- residual along x1, r = b - (A1 (M0 x) + M1 (A0 x)) (or r = b), then Sᵀ along x1
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / m, i0 = task - q * m;
+      if (task < NB && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
+        T res[m];
+        if constexpr (ADD) {
+#pragma unroll
+          for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
+        } else {
+          const T* PM = bufA;
+          const T* PA = bufA + PPW * n * m;
+          T pm[n], pa[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
             pm[j] = PM[(q * n + j) * m + i0];
             pa[j] = PA[(q * n + j) * m + i0];
           }
-          const long long gb = (s1 + 1) * n1d + (s0 + 2 * K * q + 1 + i0);
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T s = T(0);
@@ -354,68 +437,54 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
               s = fma(tb.Ac[i * n + j], pm[j], s);
               s = fma(tb.Mc[i * n + j], pa[j], s);
             }
-            res[i] = b[gb + i * n1d] - res_scale * s;
-          }
-#pragma unroll
-          for (int a = 0; a < m; ++a) {
-            T s = T(0);
-#pragma unroll
-            for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
-            W[(q * m + a) * m + i0] = s;
+            res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
-      }
-    } else {
-      // ---- stage 3 (additive): the input is the residual; S^T along x1
-      for (int task = tid; task < PPW * m; task += NT) {
-        const int q = task / m, i0 = task - q * m;
-        if (q < P) {
-          T res[m];
-          const long long gb = (s1 + 1) * n1d + (s0 + 2 * K * q + 1 + i0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) res[i] = b[gb + i * n1d];
+        for (int a = 0; a < m; ++a) {
+          T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) {
-            T s = T(0);
-#pragma unroll
-            for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
-            W[(q * m + a) * m + i0] = s;
-          }
+          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
+          W[(q * m + a) * m + i0] = s;
         }
       }
     }
     __syncthreads();
-    // ---- stage 4: S^T along x0, divide by eigenvalue sums, S along x0: lines (q, a1)
+    // ---- Sᵀ along x0, scale by 1/(lam1+lam0), S along x0: lines (q, a1)
     T* W2 = bufA;
-    for (int task = tid; task < PPW * m; task += NT) {
+    for (int base = 0; base < PPW * m; base += NT) {
+      const int task = base + tid;
       const int q = task / m, a1 = task - q * m;
-      if (q < P) {
+      if (task < PPW * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m], z[m];
-        const int base = (q * m + a1) * m;
+        const int basei = (q * m + a1) * m;
 #pragma unroll
-        for (int i = 0; i < m; ++i) in[i] = W[base + i];
+        for (int i = 0; i < m; ++i) in[i] = W[basei + i];
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
-          z[a] = s / (tb.lam[a1] + tb.lam[a]);
+          z[a] = s * tb.inv2[a1 * m + a];
         }
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
-          W2[base + i] = s;
+          W2[basei + i] = s;
         }
       }
     }
     __syncthreads();
-    // ---- stage 5: S along x1: lines (q, i0); correction -> LDS [q][i1][i0]
+    // ---- S along x1: lines (q, i0); correction -> LDS [q][i1][i0]
     T* E = bufB;
-    for (int task = tid; task < PPW * m; task += NT) {
+    for (int base = 0; base < PPW * m; base += NT) {
+      const int task = base + tid;
       const int q = task / m, i0 = task - q * m;
-      if (q < P) {
+      if (task < PPW * m && q < P) {
+        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W2[(q * m + a) * m + i0];
@@ -429,14 +498,16 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       }
     }
     __syncthreads();
-    // ---- stage 6: x^I += correction (rows of the segment, coalesced)
-    constexpr int RW = 2 * K * PPW;
-    for (int idx = tid; idx < m * RW; idx += NT) {
-      const int i1 = idx / RW, c = idx - i1 * RW;
+    // ---- x^I += correction.  Work item = column c; i1 walked unrolled; reads before writes.
+    for (int c = tid; c < RW; c += NT) {
       const int q = c / (2 * K), i0 = c - q * (2 * K);
       if (q < P && i0 < m) {
-        const long long g = (s1 + 1 + i1) * n1d + (s0 + 1 + c);
-        x[g] += E[(q * m + i1) * m + i0];
+        const int base = ld1 + 1 + c;
+        T old[m];
+#pragma unroll
+        for (int i1 = 0; i1 < m; ++i1) old[i1] = xo[base + i1 * ld1];
+#pragma unroll
+        for (int i1 = 0; i1 < m; ++i1) xo[base + i1 * ld1] = old[i1] + E[(q * m + i1) * m + i0];
       }
     }
   }
@@ -458,6 +529,10 @@ static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void
   const int groups0 = (cnt[0] + PPW - 1) / PPW;
   const long long blocks = (long long)groups0 * cnt[1] * (D == 3 ? cnt[2] : 1);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  // the kernel addresses one workgroup's block with 32-bit offsets
+  constexpr long long n = 2 * K + 1;
+  const long long span = (D == 3 ? (n - 1) * g.n1d * g.n1d : 0) + (n - 1) * g.n1d + 2 * K * PPW + 1;
+  if (span >= (1LL << 31)) return hipErrorInvalidValue;
   // Abar_h = h^(d-2) Abar_1 ; A_j,h^{-1} = h^(2-d) A_j,1^{-1}
   const double h = g.h;
   const T res_scale = (T)(D == 3 ? h : 1.0);
