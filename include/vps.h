@@ -64,7 +64,8 @@ enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
 #define VPS_FLAG_FP32_HIERARCHY 0x2u /* allocate FP32 V-cycle scratch (needed by FP32 vcycle / mixed solve) */
 #define VPS_FLAG_NO_SOLVER 0x4u      /* skip the outer-CG vectors (vps_pcg_solve then fails with VPS_EINVAL) */
 #define VPS_FLAG_POST_SAME_ORDER 0x8u /* post-smoothing colours ascending (Alg. 1 read literally; the
-                                         V-cycle is then not symmetric).  Default: descending. */
+                                         V-cycle is then not symmetric and vps_pcg_solve uses the flexible
+                                         beta in both modes).  Default: descending (symmetric V-cycle). */
 
 typedef struct vps_problem vps_problem;
 
@@ -146,7 +147,8 @@ int vps_vcycle(vps_problem* p, int prec, const void* b, void* x);
  * b, x: FP64 device vectors.  VPS_SOLVE_FP64: FP64 V-cycle, standard CG.
  * VPS_SOLVE_MIXED: the residual is rounded to FP32, one FP32 V-cycle (FP64 coarse solve)
  * approximates the error, the correction is widened to FP64; residuals, dot products and
- * updates stay FP64 (Sec. 4.2); CG uses the flexible (Polak-Ribiere) beta.
+ * updates stay FP64 (Sec. 4.2); CG uses the flexible (Polak-Ribiere) beta (also in FP64 mode
+ * when the problem was created with VPS_FLAG_POST_SAME_ORDER).
  * Stops when ||r||_2 <= rtol ||b||_2.  Synchronises once per iteration; fills *stats
  * (may be NULL).  Returns VPS_OK, VPS_ENOCONV, VPS_EBREAKDOWN or VPS_ENOTFINITE. */
 int vps_pcg_solve(vps_problem* p, int solve_mode, const double* b, double* x, double rtol, int maxit,

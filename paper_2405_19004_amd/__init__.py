@@ -11,7 +11,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvps.so")
+# VPS_LIB may name another build of the same library (A/B timing of kernel variants).
+LIB_PATH = os.environ.get("VPS_LIB") or os.path.join(_HERE, "libvps.so")
 
 VPS_OK, VPS_EINVAL, VPS_ENOMEM, VPS_EHIP, VPS_ENOCONV, VPS_EBREAKDOWN, VPS_ENOTFINITE, VPS_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 VPS_FP64, VPS_FP32 = 0, 1

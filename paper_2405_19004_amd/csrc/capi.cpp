@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vps.h"
+#include "vps.h"
 #include "kernels.hpp"
 #include "problem.hpp"
 #include "tables.hpp"
@@ -226,8 +226,10 @@ int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, v
     if (int e = check_level(p, fine_level, 2)) return e;
     if (int e = check_prec(prec)) return e;
     if (!r_fine || !r_coarse) return fail(VPS_EINVAL, "null vector");
-    hipError_t e = vps::launch_restrict(p->impl->geom(fine_level), prec, r_fine, r_coarse, p->impl->stream);
-    if (e == hipSuccess) e = vps::launch_zero_boundary(p->impl->geom(fine_level - 1), prec, r_coarse, p->impl->stream);
+    const vps::LevelBuffers& B = p->impl->lv[fine_level];
+    if (!B.t1[prec]) return fail(VPS_EINVAL, "restriction in this precision needs the matching hierarchy flag");
+    hipError_t e = vps::launch_restrict(p->impl->geom(fine_level), prec, r_fine, r_coarse, B.t1[prec], B.t2[prec],
+                                        p->impl->stream);
     return e == hipSuccess ? VPS_OK : fail(VPS_EHIP, std::string("restrict launch: ") + hipGetErrorString(e));
   });
 }

@@ -80,9 +80,9 @@ __device__ __forceinline__ void load_row(T (&in)[N], const T* __restrict__ row, 
 template <int D, int K>
 struct OpShape {
   static constexpr int C0 = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K <= 4 ? 8 : 4) : (16 / K > 1 ? 16 / K : 1);
-  static constexpr int C1 = D == 2 ? (K == 1 ? 8 : K <= 3 ? 4 : 2) : (K == 1 ? 4 : K <= 3 ? 2 : 1);
+  static constexpr int C1 = D == 2 ? (K == 1 ? 8 : K <= 3 ? 4 : 2) : (K == 1 ? 8 : K <= 4 ? 2 : 1);
   static constexpr int C2 = D == 3 ? C1 : 1;
-  static constexpr int NT = 128;
+  static constexpr int NT = D == 3 && K <= 4 ? 256 : 128;
 };
 
 template <int D, int K, typename T, bool RESID>
@@ -445,6 +445,98 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   }
 }
 
+// -------------------------------------------------- separable restriction
+
+// One axis of r_coarse = (P1 x P1 x P1)^T r_fine.  `out` has extents (o2, o1, o0); `in` has the
+// same extents except along AXIS, where it has the fine length nf (out has the coarse length nc).
+// Coarse node J = k*C + a collects fine nodes 2k(C-1) + t with weights Rb[a][t] (t in [0, 4k] for
+// a vertex, [2k, 4k] otherwise).  Fine boundary nodes along AXIS are read as 0 and coarse
+// boundary nodes along AXIS are written 0; in the first pass (`mask_other`) outputs on the
+// Dirichlet boundary of the other, still fine, axes are written 0 too.  One thread per output,
+// lanes along x0, the other two coordinates from the grid (no index division): coalesced.
+template <int K, typename T, int AXIS>
+__global__ void restrict_pass_kernel(const T* __restrict__ in, T* __restrict__ out, int nf, int nc, int o0, int o1,
+                                     int o2) {
+  constexpr int RW = 4 * K + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // (i1, i0) of one output plane
+  if (t >= o0 * o1) return;
+  const int i1 = t / o0, i0 = t - i1 * o0;
+  const long long ie0 = AXIS == 0 ? nf : o0, ie1 = AXIS == 1 ? nf : o1;
+  const long long stride = AXIS == 0 ? 1 : AXIS == 1 ? ie0 : ie0 * ie1;
+  const DevTables<T>& tb = gtab<T>(K);
+  for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
+    const long long oidx = ((long long)i2 * o1 + i1) * o0 + i0;
+    const int J = AXIS == 0 ? i0 : AXIS == 1 ? i1 : i2;
+    if (J == 0 || J == nc - 1) {
+      out[oidx] = T(0);
+      continue;
+    }
+    const long long base = AXIS == 0 ? ((long long)i2 * ie1 + i1) * ie0
+                         : AXIS == 1 ? (long long)i2 * ie1 * ie0 + i0
+                                     : (long long)i1 * ie0 + i0;
+    const T* p = in + base;
+    const int a = J % K;
+    const int f0 = 2 * (J - a) - 2 * K;  // fine index of band position 0
+    T s = T(0);
+    if (a == 0) {
+#pragma unroll
+      for (int tt = 0; tt < RW; ++tt) {
+        const int f = f0 + tt;
+        const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
+        const T v = p[fc * stride];
+        s = fma(tb.Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
+      }
+    } else {
+#pragma unroll
+      for (int tt = 2 * K; tt < RW; ++tt) {
+        const int f = f0 + tt;  // in [1, nf - 2] for a cell-interior coarse node
+        s = fma(tb.Rb[a * RW + tt], p[f * stride], s);
+      }
+    }
+    out[oidx] = s;
+  }
+}
+
+// First restriction pass, along x0: one thread per coarse cell C writes the k coarse nodes
+// k*C .. k*C+k-1 (every node class, so the band structure is compile-time) from the fine window
+// 2k(C-1) .. 2k(C+1) held in registers.  `in` has extents (o2, o1, nf), `out` (o2, o1, nc); rows
+// on the Dirichlet boundary of the (still fine) other axes are written 0.
+template <int K, typename T>
+__global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out, int nf, int nc, int o1, int o2) {
+  constexpr int RW = 4 * K + 1;
+  const int ncc = (nc - 1) / K;  // coarse cells along x0
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // (i1, C)
+  if (t >= (ncc + 1) * o1) return;
+  const int i1 = t / (ncc + 1), C = t - i1 * (ncc + 1);
+  const DevTables<T>& tb = gtab<T>(K);
+  for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
+    const bool row_zero = i1 == 0 || i1 == nf - 1 || (o2 > 1 && (i2 == 0 || i2 == nf - 1));
+    const long long row = (long long)i2 * o1 + i1;
+    T* q = out + row * nc;
+    if (C == ncc) {
+      q[nc - 1] = T(0);
+      continue;
+    }
+    const T* p = in + row * nf;
+    const int f0 = 2 * K * (C - 1);
+    T w[RW];
+#pragma unroll
+    for (int tt = 0; tt < RW; ++tt) {
+      const int f = f0 + tt;
+      const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
+      const T v = p[fc];
+      w[tt] = (f > 0 && f < nf - 1) ? v : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma(tb.Rb[a * RW + tt], w[tt], s);
+      q[K * C + a] = (row_zero || (a == 0 && C == 0)) ? T(0) : s;
+    }
+  }
+}
+
 // ------------------------------------------------------- boundary and rhs
 
 // Zero every boundary node: thread per node of the d-1 dimensional faces.
@@ -526,14 +618,30 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
 }
 
 template <int D, int K, typename T>
-hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st) {
-  using S = ResShape<D, K>;
-  const long long ncc = fine.ncells / 2;
-  const int tiles = ceil_div(ncc, S::C);
-  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
-  const long long n1dc = (long long)K * ncc + 1;
-  hipLaunchKernelGGL((restrict_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)rf, (T*)rc,
-                     n1dc, fine.n1d, tiles);
+hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t1, void* t2) {
+  const int nf = (int)fine.n1d, nc = (int)(K * (fine.ncells / 2) + 1);
+  const int ncc = (nc - 1) / K;
+  // grid x: 256-thread blocks over one output plane (rows flattened); grid y: planes
+  auto g = [](long long plane, int planes) {
+    return dim3((unsigned)((plane + 255) / 256), (unsigned)(planes < 65535 ? planes : 65535));
+  };
+  if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
+    return hipErrorInvalidConfiguration;
+  if (D == 2) {
+    // x0: [nf][nf] -> T1 [nf][nc]; x1: T1 -> rc [nc][nc]
+    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, 1), dim3(256), 0, st, (const T*)rf,
+                       (T*)t1, nf, nc, nf, 1);
+    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), g((long long)nc * nc, 1), dim3(256), 0, st, (const T*)t1,
+                       (T*)rc, nf, nc, nc, nc, 1);
+  } else {
+    // x0: [nf][nf][nf] -> T1 [nf][nf][nc]; x1: T1 -> T2 [nf][nc][nc]; x2: T2 -> rc [nc][nc][nc]
+    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, nf), dim3(256), 0, st, (const T*)rf,
+                       (T*)t1, nf, nc, nf, nf);
+    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), g((long long)nc * nc, nf), dim3(256), 0, st, (const T*)t1,
+                       (T*)t2, nf, nc, nc, nc, nf);
+    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 2>), g((long long)nc * nc, nc), dim3(256), 0, st, (const T*)t2,
+                       (T*)rc, nf, nc, nc, nc, nc);
+  }
   return hipGetLastError();
 }
 
@@ -583,8 +691,9 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
   VPS_DISPATCH(pro_launch, fine, prec, e, xf, st);
 }
 
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, hipStream_t st) {
-  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st);
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t1, void* t2,
+                           hipStream_t st) {
+  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t1, t2);
 }
 
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st) {

@@ -24,6 +24,31 @@ enum : int {
 };
 
 hipError_t init_smoother_tables();
+
+// One member of a packed colour-pass launch (see launch_colour_pass_group).
+struct ColourPassDesc {
+  const void* b;
+  void* x;
+  long long n1d;
+  int p[3];
+  int cnt0, cnt1, groups0;
+  int block_begin;
+  double res_scale, sol_scale;
+};
+constexpr int kMaxGroup = 16;
+struct ColourPassGroup {
+  int n;
+  ColourPassDesc e[kMaxGroup];
+};
+struct ColourPassMember {
+  LevelGeom g;
+  const void* b;
+  void* x;
+};
+// Colour `colour` on every member (same dim, degree and precision; any levels) with one launch
+// per kMaxGroup members.  Each member's arithmetic is exactly that of launch_colour_pass.
+hipError_t launch_colour_pass_group(int dim, int k, int prec, bool additive, int colour,
+                                    const ColourPassMember* members, int n_members, hipStream_t st);
 hipError_t init_grid_tables();
 
 // smoother.hip
@@ -32,7 +57,13 @@ hipError_t launch_colour_pass(const LevelGeom& g, int prec, bool additive, int c
 
 // grid.hip (interior outputs only)
 hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b_or_null, void* y, hipStream_t st);
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, hipStream_t st);
+// Restriction in separable passes; t1, t2 are scratch of restrict_scratch_elems(fine) elements each.
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t1, void* t2,
+                           hipStream_t st);
+inline long long restrict_scratch_elems(int dim, int k, int fine_level) {
+  const long long nf = (long long)k * (1LL << fine_level) + 1, nc = (long long)k * (1LL << (fine_level - 1)) + 1;
+  return dim == 2 ? nf * nc : nf * nf * nc;
+}
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st);
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);
 hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const double* G, const double* coef, void* b,

@@ -62,7 +62,12 @@ Plan plan(int dim, int k, int L, unsigned flags) {
         pl.sizes.push_back(N * es);  // b
         pl.sizes.push_back(N * es);  // x
       }
-      if (lvl >= 2) pl.sizes.push_back(N * es);  // r
+      if (lvl >= 2) {
+        pl.sizes.push_back(N * es);  // r
+        const size_t T = (size_t)restrict_scratch_elems(dim, k, lvl) * es;
+        pl.sizes.push_back(T);  // restriction scratch t1
+        pl.sizes.push_back(T);  // t2
+      }
     }
   }
   if (h32) {
@@ -148,7 +153,11 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
         B.b[prec] = p->allocs[idx++];
         B.x[prec] = p->allocs[idx++];
       }
-      if (lvl >= 2) B.r[prec] = p->allocs[idx++];
+      if (lvl >= 2) {
+        B.r[prec] = p->allocs[idx++];
+        B.t1[prec] = p->allocs[idx++];
+        B.t2[prec] = p->allocs[idx++];
+      }
     }
   }
   if (h32) {
@@ -219,7 +228,8 @@ Status vcycle(Problem* p, int prec, const void* bL, void* xL) {
     if (lvl < L) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
     VPS_TRY(smoother(p, lvl, prec, kMult, false, b, x));
     VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
-    VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->stream));
+    VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
+                            p->lv[lvl].t2[prec], p->stream));
   }
   VPS_TRY(coarse_solve(p, prec, p->lv[1].b[prec], p->lv[1].x[prec]));
   // ascend
@@ -232,9 +242,55 @@ Status vcycle(Problem* p, int prec, const void* bL, void* xL) {
   return Status::ok();
 }
 
-// ------------------------------------------------------------------------ CG
+Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL) {
+  if (n <= 0) return Status::ok();
+  int Lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ps[i]->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
+    if (ps[i]->dim != ps[0]->dim || ps[i]->k != ps[0]->k || ps[i]->stream != ps[0]->stream ||
+        ps[i]->post_same_order != ps[0]->post_same_order)
+      return Status{-1, "grouped V-cycle needs one dim, degree, stream and colour order"};
+    Lmax = ps[i]->L > Lmax ? ps[i]->L : Lmax;
+  }
+  const int dim = ps[0]->dim, k = ps[0]->k, nc = 1 << dim;
+  const bool post_rev = !ps[0]->post_same_order;
+  hipStream_t st = ps[0]->stream;
+  auto level_b = [&](int i, int lvl) -> const void* { return lvl == ps[i]->L ? bL[i] : ps[i]->lv[lvl].b[prec]; };
+  auto level_x = [&](int i, int lvl) -> void* { return lvl == ps[i]->L ? xL[i] : ps[i]->lv[lvl].x[prec]; };
+  std::vector<ColourPassMember> mem;
+  auto smooth = [&](int lvl, bool reverse) -> Status {
+    mem.clear();
+    for (int i = 0; i < n; ++i)
+      if (ps[i]->L >= lvl) mem.push_back({ps[i]->geom(lvl), level_b(i, lvl), level_x(i, lvl)});
+    for (int j = 0; j < nc; ++j) {
+      const int c = reverse ? nc - 1 - j : j;
+      VPS_HIP(launch_colour_pass_group(dim, k, prec, false, c, mem.data(), (int)mem.size(), st));
+    }
+    return Status::ok();
+  };
+  for (int lvl = Lmax; lvl >= 2; --lvl) {
+    for (int i = 0; i < n; ++i)
+      if (ps[i]->L > lvl) VPS_HIP(launch_fill(prec, level_x(i, lvl), ps[i]->lv[lvl].N, 0.0, st));
+    VPS_TRY(smooth(lvl, false));
+    for (int i = 0; i < n; ++i) {
+      if (ps[i]->L < lvl) continue;
+      Problem* p = ps[i];
+      VPS_HIP(launch_operator(p->geom(lvl), prec, level_x(i, lvl), level_b(i, lvl), p->lv[lvl].r[prec], st));
+      VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
+                              p->lv[lvl].t2[prec], st));
+    }
+  }
+  for (int i = 0; i < n; ++i) VPS_TRY(coarse_solve(ps[i], prec, level_b(i, 1), level_x(i, 1)));
+  for (int lvl = 2; lvl <= Lmax; ++lvl) {
+    for (int i = 0; i < n; ++i)
+      if (ps[i]->L >= lvl)
+        VPS_HIP(launch_prolongate_add(ps[i]->geom(lvl), prec, ps[i]->lv[lvl - 1].x[prec], level_x(i, lvl), st));
+    VPS_TRY(smooth(lvl, post_rev));
+  }
+  return Status::ok();
+}
 
-namespace {
+// ------------------------------------------------------------------------ CG
 
 Status precondition(Problem* p, int mode, const double* r, double* z) {
   const long long N = p->lv[p->L].N;
@@ -250,7 +306,33 @@ Status precondition(Problem* p, int mode, const double* r, double* z) {
   return Status::ok();
 }
 
-}  // namespace
+Status precondition_group(Problem* const* ps, int n, int mode) {
+  const int prec = mode == 0 ? 0 : 1;
+  std::vector<const void*> bs(n);
+  std::vector<void*> xs(n);
+  for (int i = 0; i < n; ++i) {
+    Problem* p = ps[i];
+    const long long N = p->lv[p->L].N;
+    if (mode == 0) {
+      VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
+      bs[i] = p->r;
+      xs[i] = p->z;
+    } else {
+      LevelBuffers& B = p->lv[p->L];
+      VPS_HIP(launch_cast(0, p->r, B.b[1], N, p->stream));
+      VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
+      bs[i] = B.b[1];
+      xs[i] = B.x[1];
+    }
+  }
+  VPS_TRY(vcycle_group(ps, n, prec, bs.data(), xs.data()));
+  if (mode != 0)
+    for (int i = 0; i < n; ++i) {
+      Problem* p = ps[i];
+      VPS_HIP(launch_cast(1, p->lv[p->L].x[1], p->z, p->lv[p->L].N, p->stream));
+    }
+  return Status::ok();
+}
 
 Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) {
   if (!p->r) return Status{-1, "problem was created without solver vectors"};
@@ -292,8 +374,8 @@ Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
   return Status::ok();
 }
 
-Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
-  const long long N = p->lv[p->L].N;
+Status pcg_decide(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
+  (void)mode;
   const double pq = p->host_sc[kScPQ], rz = p->host_sc[kScRZ], rr = p->host_sc[kScRR];
   cs->it += 1;
   cs->stats.iterations = cs->it;
@@ -307,18 +389,28 @@ Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState*
   if (cs->rel <= rtol) {
     cs->done = true;
     cs->stats.status = 0;
-    return Status::ok();
-  }
-  if (cs->it >= maxit) {
+  } else if (cs->it >= maxit) {
     cs->done = true;
     cs->stats.status = -4;
-    return Status::ok();
   }
-  VPS_TRY(precondition(p, mode, p->r, p->z));
+  return Status::ok();
+}
+
+Status pcg_after_precond(Problem* p, int mode) {
+  const long long N = p->lv[p->L].N;
   VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
-  VPS_HIP(launch_cg_beta(p->sc, mode == 1 ? 1 : 0, p->stream));
+  // flexible (Polak-Ribiere) beta whenever the preconditioner is not symmetric: FP32 V-cycle
+  // (rounding) or the literal colour order after the coarse correction
+  VPS_HIP(launch_cg_beta(p->sc, (mode == 1 || p->post_same_order) ? 1 : 0, p->stream));
   VPS_HIP(launch_cg_direction(p->p, p->z, N, p->sc, p->stream));
   return Status::ok();
+}
+
+Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
+  VPS_TRY(pcg_decide(p, mode, rtol, maxit, cs));
+  if (cs->done) return Status::ok();
+  VPS_TRY(precondition(p, mode, p->r, p->z));
+  return pcg_after_precond(p, mode);
 }
 
 Status pcg_end(Problem* p, const double* b, double* x, CgState* cs) {

@@ -22,6 +22,8 @@ struct LevelBuffers {
   void* b[2] = {nullptr, nullptr};  // V-cycle right-hand side per precision (levels < L; FP32 also L)
   void* x[2] = {nullptr, nullptr};  // V-cycle iterate per precision
   void* r[2] = {nullptr, nullptr};  // residual per precision (levels >= 2)
+  void* t1[2] = {nullptr, nullptr}; // restriction scratch per precision (levels >= 2)
+  void* t2[2] = {nullptr, nullptr};
 };
 
 struct Problem {
@@ -61,6 +63,10 @@ Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const v
 Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x);
 Status coarse_solve(Problem* p, int prec, const void* b, void* x);
 Status vcycle(Problem* p, int prec, const void* b, void* x);
+// V-cycles of n problems of the same (dim, degree), all on one stream, in lockstep: every colour
+// pass of a level is one packed launch over the problems that have that level.  Each problem's
+// arithmetic (and result) is exactly that of vcycle() on it alone.
+Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL);
 
 struct SolveStats {
   int iterations = 0;
@@ -79,6 +85,12 @@ struct CgState {
 Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs);
 Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs);   // enqueue one iteration up to the norm copy
 Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync: decide, enqueue precond
+// pcg_iterate_finish in parts, for callers that precondition several problems together:
+Status pcg_decide(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync; no launches
+Status pcg_after_precond(Problem* p, int mode);  // z is ready: r.z, beta, new direction
+// z = M r (FP64 V-cycle, or FP32 V-cycle between casts) for one problem / a group (same dim, degree)
+Status precondition(Problem* p, int mode, const double* r, double* z);
+Status precondition_group(Problem* const* ps, int n, int mode);  // z_i = M r_i with each problem's CG vectors
 Status pcg_end(Problem* p, const double* b, double* x, CgState* cs);
 
 }  // namespace vps

@@ -5,12 +5,14 @@
 // device footprint fits the remaining memory budget; idle hierarchies of
 // finished requests are cached per (dim, degree, level, mode) and handed to
 // later requests of the same shape, and evicted (least recently used first)
-// when a new shape needs their memory.  Every admitted request owns a HIP
-// stream, so the work of different requests overlaps on the device.  A tick
-// enqueues one CG iteration for every active request, waits for all of them,
-// then retires converged requests and enqueues the next preconditioner calls.
-// Each request runs exactly the arithmetic of a stand-alone vps_pcg_solve with
-// the same deterministic kernels, so its result does not depend on the mix.
+// when a new shape needs their memory.  Requests of the same (dim, degree,
+// solve mode) form a group with one HIP stream; different groups overlap on
+// the device.  A tick enqueues one CG iteration for every active request,
+// waits, retires converged requests, then preconditions every group with one
+// batched V-cycle whose smoother colour passes are packed into one launch per
+// (level, colour) across the group's requests (levels may differ).  Each
+// request runs exactly the arithmetic of a stand-alone vps_pcg_solve with the
+// same deterministic kernels, so its result does not depend on the mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,7 +23,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/vps.h"
+#include "vps.h"
 #include "problem.hpp"
 
 namespace {
@@ -61,6 +63,7 @@ struct vps_server {
   std::map<long long, Request*> all;
   std::list<Slot> idle;  // cached hierarchies, most recently used at the front
   size_t in_use = 0, cached = 0;
+  std::map<std::tuple<int, int, int>, hipStream_t> streams;  // per (dim, degree, mode)
 };
 
 namespace {
@@ -71,10 +74,22 @@ int sfail(int code, const std::string& m) {
 }
 
 void free_slot(Slot& s) {
-  delete s.prob;
-  if (s.stream) hipStreamDestroy(s.stream);
+  delete s.prob;  // synchronises the problem's (group) stream
   s.prob = nullptr;
   s.stream = nullptr;
+}
+
+hipStream_t group_stream(vps_server* S, int dim, int k, int mode) {
+  auto key = std::make_tuple(dim, k, mode);
+  auto it = S->streams.find(key);
+  if (it != S->streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  S->streams[key] = st;
+  return st;
 }
 
 // Try to give request r a hierarchy.  Returns 1 on success, 0 if it must wait, <0 on error.
@@ -99,15 +114,10 @@ int acquire(vps_server* S, Request* r) {
   Slot s;
   s.key = key;
   s.bytes = r->bytes;
-  if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipGetLastError();
-    return sfail(VPS_EHIP, "hipStreamCreate failed");
-  }
+  s.stream = group_stream(S, r->dim, r->k, r->mode);
+  if (!s.stream) return sfail(VPS_EHIP, "hipStreamCreate failed");
   vps::Status st = vps::create_problem(r->dim, r->k, r->level, flags_for(r->mode), s.stream, &s.prob);
-  if (st.code) {
-    hipStreamDestroy(s.stream);
-    return sfail(st.code, st.msg);
-  }
+  if (st.code) return sfail(st.code, st.msg);
   S->in_use += s.bytes;
   r->slot = s;
   return 1;
@@ -188,16 +198,17 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
     }
     s->active.push_back(r);
   }
-  // one CG iteration for every active request, overlapped across streams
+  // one CG iteration for every active request (groups overlap on their streams)
   for (Request* r : s->active) {
     vps::Status st = vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
     if (st.code) return sfail(st.code, st.msg);
   }
-  for (Request* r : s->active)
-    if (hipStreamSynchronize(r->slot.stream) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
+  for (auto& kv : s->streams)
+    if (hipStreamSynchronize(kv.second) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
   std::vector<Request*> still;
+  std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
   for (Request* r : s->active) {
-    vps::Status st = vps::pcg_iterate_finish(r->slot.prob, r->mode, r->rtol, r->maxit, &r->cs);
+    vps::Status st = vps::pcg_decide(r->slot.prob, r->mode, r->rtol, r->maxit, &r->cs);
     if (st.code) return sfail(st.code, st.msg);
     if (r->cs.done) {
       st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
@@ -206,6 +217,18 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
       release(s, r);
     } else {
       still.push_back(r);
+      groups[std::make_tuple(r->dim, r->k, r->mode)].push_back(r);
+    }
+  }
+  // preconditioner: one batched V-cycle per group, colour passes packed across its requests
+  for (auto& kv : groups) {
+    std::vector<vps::Problem*> ps;
+    for (Request* r : kv.second) ps.push_back(r->slot.prob);
+    vps::Status st = vps::precondition_group(ps.data(), (int)ps.size(), std::get<2>(kv.first));
+    if (st.code) return sfail(st.code, st.msg);
+    for (Request* r : kv.second) {
+      st = vps::pcg_after_precond(r->slot.prob, r->mode);
+      if (st.code) return sfail(st.code, st.msg);
     }
   }
   s->active.swap(still);
@@ -232,10 +255,10 @@ int vps_server_memory(vps_server* s, size_t* in_use, size_t* cached) {
 
 int vps_server_destroy(vps_server* s) {
   if (!s) return VPS_OK;
-  for (Request* r : s->active)
-    if (r->slot.stream) hipStreamSynchronize(r->slot.stream);
+  for (auto& kv : s->streams) (void)hipStreamSynchronize(kv.second);
   for (Request* r : s->active) free_slot(r->slot);
   for (Slot& sl : s->idle) free_slot(sl);
+  for (auto& kv : s->streams) (void)hipStreamDestroy(kv.second);
   for (auto& kv : s->all) delete kv.second;
   delete s;
   return VPS_OK;

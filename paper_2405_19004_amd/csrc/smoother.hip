@@ -44,27 +44,59 @@ template <int K> struct SmootherShape<2, K> {
   static constexpr int PPW = K == 1 ? 64 : K == 2 ? 32 : K == 3 ? 16 : K <= 5 ? 12 : 8;
   static constexpr int NT = 128;
 };
+#ifndef VPS_Q4_3D_PPW
+#define VPS_Q4_3D_PPW 2
+#endif
+#ifndef VPS_Q4_3D_NT
+#define VPS_Q4_3D_NT 128
+#endif
 template <int K> struct SmootherShape<3, K> {
-  static constexpr int PPW = K == 1 ? 32 : K == 2 ? 8 : K == 3 ? 4 : K == 4 ? 2 : 1;
-  static constexpr int NT = K <= 4 ? 128 : K == 5 ? 128 : K == 6 ? 192 : 256;
+  static constexpr int PPW = K == 1 ? 32 : K == 2 ? 8 : K == 3 ? 4 : K == 4 ? VPS_Q4_3D_PPW : 1;
+  static constexpr int NT = K == 4 ? VPS_Q4_3D_NT : K <= 5 ? 128 : K == 6 ? 192 : 256;
 };
 
+// Smallest s >= v with s = r (mod 32): padded outer strides of the LDS transpose buffers.
+constexpr int pad32(int v, int r) { return v + ((r - v) % 32 + 32) % 32; }
+
+// LDS layouts.  Every transpose buffer puts the loop axis of the stage that reads it outermost,
+// so the reading lanes touch consecutive words; the outer stride is padded (mod 32) so that the
+// writing lanes of the previous stage also fall into distinct banks.
 template <int D, int K, typename T, bool ADD>
 struct SmootherLds {
   static constexpr int n = 2 * K + 1, m = 2 * K - 1;
   static constexpr int PPW = SmootherShape<D, K>::PPW;
   static constexpr int RS = 2 * K * PPW + 1;  // closure row segment of the workgroup
-  static constexpr int X = ADD ? 0 : (D == 3 ? n * n * RS : n * RS);
-  static constexpr int A3 = ADD ? PPW * m * m * m : (2 * PPW * n * n * m > PPW * m * m * m ? 2 * PPW * n * n * m : PPW * m * m * m);
-  static constexpr int B3 = ADD ? PPW * m * m * m : (2 * PPW * n * m * m > PPW * m * m * m ? 2 * PPW * n * m * m : PPW * m * m * m);
-  static constexpr int A2 = ADD ? PPW * m * m : (2 * PPW * n * m > PPW * m * m ? 2 * PPW * n * m : PPW * m * m);
-  static constexpr int B2 = PPW * m * m;
-  static constexpr int BX3 = X > B3 ? X : B3;
-  static constexpr int BX2 = X > B2 ? X : B2;
-  static constexpr int total = D == 3 ? A3 + BX3 : A2 + BX2;
+  // ---- 3D strides
+  // residue of the P stride that makes the x0-contraction writes conflict-free (searched per degree
+  // for the launch shapes above, 4- and 8-byte words)
+  static constexpr int kSJ1Res[8] = {0, 11, 7, 19, 15, 27, 23, 3};
+  static constexpr int SJ1 = pad32(PPW * n * m, kSJ1Res[K]);  // P  [j1][q][j2][i0]   (PM, PA)
+  static constexpr int SJ2 = pad32(PPW * m * m, m);          // UV [j2][q][i1][i0]   (U, V)
+  static constexpr int SI1 = pad32(PPW * m * m, m);          // W4 [i1][q][a2][i0]
+  static constexpr int SI0 = pad32(PPW * m * m, 1);          // W5 [i0][q][a2][a1]
+  static constexpr int SA1 = pad32(PPW * m * m, 1);          // W6 [a1][q][a2][i0]
+  static constexpr int SA2 = pad32(PPW * m * m, m);          // W7 [a2][q][i1][i0]
+  static constexpr int X3 = ADD ? 0 : n * n * RS;
+  static constexpr int P3 = ADD ? 0 : 2 * n * SJ1;
+  static constexpr int UV3 = ADD ? 0 : 2 * n * SJ2;
+  static constexpr int A3 = P3 > m * SI1 ? (P3 > m * SA1 ? P3 : m * SA1) : (m * SI1 > m * SA1 ? m * SI1 : m * SA1);
+  static constexpr int B3a = X3 > UV3 ? X3 : UV3;
+  static constexpr int B3b = m * SI0 > m * SA2 ? m * SI0 : m * SA2;
+  static constexpr int B3 = B3a > B3b ? B3a : B3b;
+  // ---- 2D strides
+  static constexpr int T1 = pad32(PPW * m, (m * PPW) % 32);  // P2  [j1][q][i0]  (PM, PA)
+  static constexpr int T0 = pad32(PPW * m, 1);               // W   [i0][q][a1]
+  static constexpr int TA = pad32(PPW * m, 1);               // W2  [a1][q][i0]
+  static constexpr int X2 = ADD ? 0 : n * RS;
+  static constexpr int P2 = ADD ? 0 : 2 * n * T1;
+  static constexpr int A2 = P2 > m * TA ? P2 : m * TA;
+  static constexpr int B2 = X2 > m * T0 ? X2 : m * T0;
+  static constexpr int total = D == 3 ? A3 + B3 : A2 + B2;
   static constexpr int offA = 0;
   static constexpr int offB = D == 3 ? A3 : A2;
 };
+
+__device__ __forceinline__ bool on_boundary(long long i, long long n1d) { return i == 0 || i == n1d - 1; }
 
 // The constant tables re-derived through an opaque (but wave-uniform) zero
 // offset: keeps the compiler from hoisting every table load out of a stage's
@@ -76,20 +108,20 @@ __device__ __forceinline__ const DevTables<T>& tab_fresh(int k) {
   return *reinterpret_cast<const DevTables<T>*>(reinterpret_cast<const char*>(&tab<T>(k)) + z);
 }
 
+// One workgroup's share of a colour pass: patches of block `blk` of the colour described by
+// (p0, p1, p2, cnt0, cnt1, groups0) on a level with n1d nodes per direction.
 template <int D, int K, typename T, bool ADD>
-__global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
-    const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
-    int groups0, T res_scale, T sol_scale) {
-  constexpr int n = 2 * K + 1, m = 2 * K - 1;
+__device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T* __restrict__ b, T* __restrict__ x,
+                                                  long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
+                                                  int groups0, T res_scale, T sol_scale, unsigned blk) {
+  constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
   constexpr int PPW = SmootherShape<D, K>::PPW, NT = SmootherShape<D, K>::NT;
   using L = SmootherLds<D, K, T, ADD>;
   constexpr int RS = L::RS;
-  constexpr int RW = 2 * K * PPW;  // interior row segment incl. the shared-face gaps
-  __shared__ T smem[L::total];
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
+  (void)p2;
 
-  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int g0 = blk % groups0;
   const int rest = blk / groups0;
   const int t1 = rest % cnt1;
@@ -103,44 +135,45 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
   const int tid = threadIdx.x;
   const int seg = 2 * K * P + 1;  // valid length of the closure row segment
 
-  // rows of the patch-interior block handled by stage "b" (residual/Sᵀ along the slowest axis):
-  // task = (i1, q, i0) in 3D, (q, i0) in 2D; prefetch b there before anything else.
-  constexpr int NB = D == 3 ? PPW * m * m : PPW * m;
-  constexpr int RB = (NB + NT - 1) / NT;
   // Offsets inside one workgroup's block fit in 32 bits (checked by the launcher).
   const int ld1 = (int)n1d, ld2 = D == 3 ? (int)n1d2 : 0;
   const long long origin = (D == 3 ? s2 * n1d2 : 0) + s1 * n1d + s0;  // closure corner of the first patch
-  T* xo = x + origin;  // same restrict object as x: closure loads, x^I loads and stores
+  T* xo = x + origin;  // same restrict object as x
   const T* bo = b + origin;
-  T bpre[RB][m];
+
+  // Lines along the slowest axis, task = (q, i1, i0) in 3D / (q, i0) in 2D with i0 fastest:
+  // the residual stage reads b on them and the last stage updates x^I on them.  Both are
+  // prefetched now (clamped to a valid patch so the loads are always in bounds).
+  constexpr int NB = D == 3 ? PPW * mm : PPW * m;
+  constexpr int RB = (NB + NT - 1) / NT;
+  T bpre[RB][m], xpre[RB][m];
+  int loff[RB];
 #pragma unroll
   for (int rr = 0; rr < RB; ++rr) {
     const int task = rr * NT + tid;
-    int q, i0, i1;
+    int q, i1 = 0, i0;
     if constexpr (D == 3) {
-      i1 = task / (PPW * m);
-      const int r = task - i1 * (PPW * m);
-      q = r / m;
-      i0 = r - q * m;
+      q = task / mm;
+      const int r = task - q * mm;
+      i1 = r / m;
+      i0 = r - i1 * m;
     } else {
       q = task / m;
       i0 = task - q * m;
-      i1 = 0;
     }
-    // clamp to a valid patch-interior position: the loads are then always in bounds and the
-    // values of inactive tasks are simply never used
     q = min(q, P - 1);
-    if constexpr (D == 3) i1 = min(i1, m - 1);
     const int off = (D == 3 ? ld2 + (1 + i1) * ld1 : ld1) + 2 * K * q + 1 + i0;
+    loff[rr] = off;
     const int st = D == 3 ? ld2 : ld1;
 #pragma unroll
     for (int i = 0; i < m; ++i) bpre[rr][i] = bo[off + i * st];
+#pragma unroll
+    for (int i = 0; i < m; ++i) xpre[rr][i] = xo[off + i * st];
   }
 
-  // ---- closure segment -> LDS.  Work item = (column c, row j1 in 3D); the slowest axis is
-  // walked in an unrolled loop, so an address costs one add and the Dirichlet tests on that
-  // axis are compile-time.  Every closure node lies inside the grid: loads are unconditional
-  // and Dirichlet nodes are replaced by 0 afterwards (boundary entries of x are ignored).
+  // ---- closure segment -> LDS X [j2][j1][c].  Work item = (column c, row j1 in 3D); the
+  // slowest axis is walked unrolled.  Every closure node lies inside the grid: loads are
+  // unconditional and Dirichlet nodes are replaced by 0 (boundary entries of x are ignored).
   if constexpr (!ADD) {
     T* X = bufB;
     constexpr int NW = D == 3 ? RS * n : RS;
@@ -153,16 +186,15 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
       bool bad = gc == 0 || gc == n1d - 1;
       if constexpr (D == 3) bad = bad || (j1 == 0 && lo1) || (j1 == n - 1 && hi1);
       const int base = (D == 3 ? j1 * ld1 : 0) + cl;
-      constexpr int NS = n;  // slow-axis length (j2 in 3D, j1 in 2D)
       const int sstride = D == 3 ? ld2 : ld1;
-      T v[NS];
+      T v[n];
 #pragma unroll
-      for (int j = 0; j < NS; ++j) v[j] = xo[base + j * sstride];
+      for (int j = 0; j < n; ++j) v[j] = xo[base + j * sstride];
       const bool lo = D == 3 ? lo2 : lo1, hi = D == 3 ? hi2 : hi1;
       if (c < seg) {
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-          const bool zero = bad || (j == 0 && lo) || (j == NS - 1 && hi);
+        for (int j = 0; j < n; ++j) {
+          const bool zero = bad || (j == 0 && lo) || (j == n - 1 && hi);
           X[(D == 3 ? j * n + j1 : j) * RS + c] = zero ? T(0) : v[j];
         }
       }
@@ -171,39 +203,42 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
   }
 
   if constexpr (D == 3) {
-    T* U = bufB;  // [q][j2][i1][i0]
-    T* V = bufB + PPW * n * m * m;
+    constexpr int SJ1 = L::SJ1, SJ2 = L::SJ2, SI1 = L::SI1, SI0 = L::SI0, SA1 = L::SA1, SA2 = L::SA2;
     if constexpr (!ADD) {
       const T* X = bufB;
-      T* PM = bufA;
-      T* PA = bufA + PPW * n * n * m;
-      // ---- contract x0 with Mc and Ac: lines (q, j2, j1) of n values
+      T* PM = bufA;  // [j1][q][j2][i0]
+      T* PA = bufA + n * SJ1;
+      // ---- contract x0 with Mc and Ac: lines (q, j2, j1), j1 fastest
       for (int base = 0; base < PPW * n * n; base += NT) {
         const int task = base + tid;
         const int q = task / (n * n), r = task - q * (n * n);
+        const int j2 = r / n, j1 = r - j2 * n;
         if (task < PPW * n * n && q < P) {
           const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
-          for (int j = 0; j < n; ++j) in[j] = X[r * RS + 2 * K * q + j];
+          for (int j = 0; j < n; ++j) in[j] = X[(j2 * n + j1) * RS + 2 * K * q + j];
+          const int o = j1 * SJ1 + (q * n + j2) * m;
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
-            PM[(q * n * n + r) * m + i] = sm;
+            PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
-            PA[(q * n * n + r) * m + i] = sa;
+            PA[o + i] = sa;
           }
         }
       }
       __syncthreads();
-      // ---- contract x1: lines (q, j2, i0) along j1; U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)
+      // ---- contract x1: lines (q, j2, i0), i0 fastest; U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)
+      T* U = bufB;  // [j2][q][i1][i0]
+      T* V = bufB + n * SJ2;
       for (int base = 0; base < PPW * n * m; base += NT) {
         const int task = base + tid;
         const int q = task / (n * m), r = task - q * (n * m);
@@ -211,11 +246,13 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
         if (task < PPW * n * m && q < P) {
           const DevTables<T>& tb = tab_fresh<T>(K);
           T pm[n], pa[n];
+          const int ri = task;  // = (q * n + j2) * m + i0
 #pragma unroll
           for (int j = 0; j < n; ++j) {
-            pm[j] = PM[((q * n + j2) * n + j) * m + i0];
-            pa[j] = PA[((q * n + j2) * n + j) * m + i0];
+            pm[j] = PM[j * SJ1 + ri];
+            pa[j] = PA[j * SJ1 + ri];
           }
+          const int o = j2 * SJ2 + q * mm + i0;
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T su = T(0), sv = T(0);
@@ -225,20 +262,20 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
               sv = fma(tb.Ac[i * n + j], pm[j], sv);
               sv = fma(tb.Mc[i * n + j], pa[j], sv);
             }
-            U[((q * n + j2) * m + i) * m + i0] = su;
-            V[((q * n + j2) * m + i) * m + i0] = sv;
+            U[o + i * m] = su;
+            V[o + i * m] = sv;
           }
         }
       }
       __syncthreads();
     }
-    // ---- contract x2 (residual) and apply Sᵀ along x2: lines (i1, q, i0)
-    T* W = bufA;  // [q][a2][i1][i0]
+    // ---- contract x2 (residual) and apply Sᵀ along x2: lines (q, i1, i0), i0 fastest
+    T* W4 = bufA;  // [i1][q][a2][i0]
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int task = rr * NT + tid;
-      const int i1 = task / (PPW * m), r = task - i1 * (PPW * m);
-      const int q = r / m, i0 = r - q * m;
+      const int q = task / mm, r = task - q * mm;
+      const int i1 = r / m, i0 = r - i1 * m;
       if (task < NB && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T res[m];
@@ -246,11 +283,13 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
 #pragma unroll
           for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
         } else {
+          const T* U = bufB;
+          const T* V = bufB + n * SJ2;
           T u[n], v[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
-            u[j] = U[((q * n + j) * m + i1) * m + i0];
-            v[j] = V[((q * n + j) * m + i1) * m + i0];
+            u[j] = U[j * SJ2 + task];
+            v[j] = V[j * SJ2 + task];
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
@@ -263,153 +302,148 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
+        const int o = i1 * SI1 + q * mm + i0;
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
-          W[((q * m + a) * m + i1) * m + i0] = s;
+          W4[o + a * m] = s;
         }
       }
     }
     __syncthreads();
-    // ---- Sᵀ along x1: lines (q, a2, i0)
-    T* W2 = bufB;
-    for (int base = 0; base < PPW * m * m; base += NT) {
+    // ---- Sᵀ along x1: lines (q, a2, i0), i0 fastest
+    T* W5 = bufB;  // [i0][q][a2][a1]
+    for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
-      const int q = task / (m * m), r = task - q * (m * m);
+      const int q = task / mm, r = task - q * mm;
       const int a2 = r / m, i0 = r - a2 * m;
-      if (task < PPW * m * m && q < P) {
+      if (task < PPW * mm && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
-        for (int i = 0; i < m; ++i) in[i] = W[((q * m + a2) * m + i) * m + i0];
+        for (int i = 0; i < m; ++i) in[i] = W4[i * SI1 + task];
+        const int o = i0 * SI0 + q * mm + a2 * m;
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
-          W2[((q * m + a2) * m + a) * m + i0] = s;
+          W5[o + a] = s;
         }
       }
     }
     __syncthreads();
-    // ---- Sᵀ along x0, scale by 1/(lam2+lam1+lam0), S along x0: lines (q, a2, a1)
-    for (int base = 0; base < PPW * m * m; base += NT) {
+    // ---- Sᵀ along x0, scale by 1/(lam2+lam1+lam0), S along x0: lines (q, a2, a1), a1 fastest
+    T* W6 = bufA;  // [a1][q][a2][i0]
+    for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
-      const int q = task / (m * m), r = task - q * (m * m);
-      if (task < PPW * m * m && q < P) {
+      const int q = task / mm, r = task - q * mm;
+      const int a2 = r / m, a1 = r - a2 * m;
+      if (task < PPW * mm && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m], z[m];
-        const int basei = (q * m * m + r) * m;
 #pragma unroll
-        for (int i = 0; i < m; ++i) in[i] = W2[basei + i];
+        for (int i = 0; i < m; ++i) in[i] = W5[i * SI0 + task];
+        const int li = (a2 * m + a1) * m;
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
-          z[a] = s * tb.inv3[r * m + a];
+          z[a] = s * tb.inv3[li + a];
         }
+        const int o = a1 * SA1 + q * mm + a2 * m;
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
-          W[basei + i] = s;
+          W6[o + i] = s;
         }
       }
     }
     __syncthreads();
-    // ---- S along x1: lines (q, a2, i0)
-    for (int base = 0; base < PPW * m * m; base += NT) {
+    // ---- S along x1: lines (q, a2, i0), i0 fastest
+    T* W7 = bufB;  // [a2][q][i1][i0]
+    for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
-      const int q = task / (m * m), r = task - q * (m * m);
+      const int q = task / mm, r = task - q * mm;
       const int a2 = r / m, i0 = r - a2 * m;
-      if (task < PPW * m * m && q < P) {
+      if (task < PPW * mm && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
-        for (int a = 0; a < m; ++a) in[a] = W[((q * m + a2) * m + a) * m + i0];
+        for (int a = 0; a < m; ++a) in[a] = W6[a * SA1 + task];
+        const int o = a2 * SA2 + q * mm + i0;
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
-          W2[((q * m + a2) * m + i) * m + i0] = s;
+          W7[o + i * m] = s;
         }
       }
     }
     __syncthreads();
-    // ---- S along x2: lines (q, i1, i0); correction -> LDS [q][i2][i1][i0]
-    for (int base = 0; base < PPW * m * m; base += NT) {
-      const int task = base + tid;
-      const int q = task / (m * m), r = task - q * (m * m);
-      const int i1 = r / m, i0 = r - i1 * m;
-      if (task < PPW * m * m && q < P) {
+    // ---- S along x2 and x^I += correction, straight to global: lines (q, i1, i0)
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / mm;
+      if (task < NB && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
-        for (int a = 0; a < m; ++a) in[a] = W2[((q * m + a) * m + i1) * m + i0];
+        for (int a = 0; a < m; ++a) in[a] = W7[a * SA2 + task];
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
-          W[((q * m + i) * m + i1) * m + i0] = sol_scale * s;
+          xo[loff[rr] + i * ld2] = fma(sol_scale, s, xpre[rr][i]);
         }
-      }
-    }
-    __syncthreads();
-    // ---- x^I += correction.  Work item = (column c, row i1); i2 walked unrolled; reads
-    //      issued before writes.
-    for (int w = tid; w < RW * m; w += NT) {
-      const int c = w % RW, i1 = w / RW;
-      const int q = c / (2 * K), i0 = c - q * (2 * K);
-      if (q < P && i0 < m) {
-        const int base = ld2 + (1 + i1) * ld1 + 1 + c;
-        T old[m];
-#pragma unroll
-        for (int i2 = 0; i2 < m; ++i2) old[i2] = xo[base + i2 * ld2];
-#pragma unroll
-        for (int i2 = 0; i2 < m; ++i2) xo[base + i2 * ld2] = old[i2] + W[((q * m + i2) * m + i1) * m + i0];
       }
     }
   } else {
     // ================================ 2D =====================================
-    T* W = bufB;  // [q][a1][i0]
+    constexpr int T1 = L::T1, T0 = L::T0, TA = L::TA;
     if constexpr (!ADD) {
       const T* X = bufB;
-      T* PM = bufA;
-      T* PA = bufA + PPW * n * m;
-      // ---- contract x0 with Mc and Ac: lines (q, j1)
+      T* PM = bufA;  // [j1][q][i0]
+      T* PA = bufA + n * T1;
+      // ---- contract x0 with Mc and Ac: lines (q, j1), q fastest
       for (int base = 0; base < PPW * n; base += NT) {
         const int task = base + tid;
-        const int q = task / n, j1 = task - q * n;
+        const int j1 = task / PPW, q = task - j1 * PPW;
         if (task < PPW * n && q < P) {
           const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[j1 * RS + 2 * K * q + j];
+          const int o = j1 * T1 + q * m;
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
-            PM[(q * n + j1) * m + i] = sm;
+            PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
-            PA[(q * n + j1) * m + i] = sa;
+            PA[o + i] = sa;
           }
         }
       }
       __syncthreads();
     }
-    // ---- residual along x1, r = b - (A1 (M0 x) + M1 (A0 x)) (or r = b), then Sᵀ along x1
+    // ---- residual along x1, r = b - (A1 (M0 x) + M1 (A0 x)) (or r = b), then Sᵀ along x1:
+    //      lines (q, i0), i0 fastest
+    T* W = bufB;  // [i0][q][a1]
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int task = rr * NT + tid;
@@ -422,12 +456,12 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
           for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
         } else {
           const T* PM = bufA;
-          const T* PA = bufA + PPW * n * m;
+          const T* PA = bufA + n * T1;
           T pm[n], pa[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
-            pm[j] = PM[(q * n + j) * m + i0];
-            pa[j] = PA[(q * n + j) * m + i0];
+            pm[j] = PM[j * T1 + task];
+            pa[j] = PA[j * T1 + task];
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
@@ -440,27 +474,27 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
+        const int o = i0 * T0 + q * m;
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
-          W[(q * m + a) * m + i0] = s;
+          W[o + a] = s;
         }
       }
     }
     __syncthreads();
-    // ---- Sᵀ along x0, scale by 1/(lam1+lam0), S along x0: lines (q, a1)
-    T* W2 = bufA;
+    // ---- Sᵀ along x0, scale by 1/(lam1+lam0), S along x0: lines (q, a1), a1 fastest
+    T* W2 = bufA;  // [a1][q][i0]
     for (int base = 0; base < PPW * m; base += NT) {
       const int task = base + tid;
       const int q = task / m, a1 = task - q * m;
       if (task < PPW * m && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m], z[m];
-        const int basei = (q * m + a1) * m;
 #pragma unroll
-        for (int i = 0; i < m; ++i) in[i] = W[basei + i];
+        for (int i = 0; i < m; ++i) in[i] = W[i * T0 + task];
 #pragma unroll
         for (int a = 0; a < m; ++a) {
           T s = T(0);
@@ -468,78 +502,138 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
           for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
           z[a] = s * tb.inv2[a1 * m + a];
         }
+        const int o = a1 * TA + q * m;
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
-          W2[basei + i] = s;
+          W2[o + i] = s;
         }
       }
     }
     __syncthreads();
-    // ---- S along x1: lines (q, i0); correction -> LDS [q][i1][i0]
-    T* E = bufB;
-    for (int base = 0; base < PPW * m; base += NT) {
-      const int task = base + tid;
-      const int q = task / m, i0 = task - q * m;
-      if (task < PPW * m && q < P) {
+    // ---- S along x1 and x^I += correction, straight to global: lines (q, i0)
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / m;
+      if (task < NB && q < P) {
         const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
-        for (int a = 0; a < m; ++a) in[a] = W2[(q * m + a) * m + i0];
+        for (int a = 0; a < m; ++a) in[a] = W2[a * TA + task];
 #pragma unroll
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
-          E[(q * m + i) * m + i0] = sol_scale * s;
+          xo[loff[rr] + i * ld1] = fma(sol_scale, s, xpre[rr][i]);
         }
-      }
-    }
-    __syncthreads();
-    // ---- x^I += correction.  Work item = column c; i1 walked unrolled; reads before writes.
-    for (int c = tid; c < RW; c += NT) {
-      const int q = c / (2 * K), i0 = c - q * (2 * K);
-      if (q < P && i0 < m) {
-        const int base = ld1 + 1 + c;
-        T old[m];
-#pragma unroll
-        for (int i1 = 0; i1 < m; ++i1) old[i1] = xo[base + i1 * ld1];
-#pragma unroll
-        for (int i1 = 0; i1 < m; ++i1) xo[base + i1 * ld1] = old[i1] + E[(q * m + i1) * m + i0];
       }
     }
   }
 }
 
+template <int D, int K, typename T, bool ADD>
+__global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
+    const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
+    int groups0, T res_scale, T sol_scale) {
+  __shared__ T smem[SmootherLds<D, K, T, ADD>::total];
+  colour_pass_block<D, K, T, ADD>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
+                                  xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Several colour passes of the same (dim, degree, precision, colour) on different vectors and
+// levels in one launch: entry e owns blocks [begin[e], begin[e+1]).
+template <int D, int K, typename T, bool ADD>
+__global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_group_kernel(ColourPassGroup grp) {
+  __shared__ T smem[SmootherLds<D, K, T, ADD>::total];
+  const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
+  int e = 0;
+  while (e + 1 < grp.n && (unsigned)grp.e[e + 1].block_begin <= g) ++e;
+  const ColourPassDesc& d = grp.e[e];
+  colour_pass_block<D, K, T, ADD>(smem, (const T*)d.b, (T*)d.x, d.n1d, d.p[0], d.p[1], d.p[2], d.cnt0, d.cnt1,
+                                  d.groups0, (T)d.res_scale, (T)d.sol_scale, g - (unsigned)d.block_begin);
+}
+
 // ------------------------------------------------------------------ host side
+
+// Patch grid of one colour on one level: parities, counts per axis, workgroups along x0.
+template <int D, int K>
+struct ColourGrid {
+  int p[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+  int groups0 = 0;
+  long long blocks = 0;
+  bool ok = true;  // the 32-bit block offsets of the kernel are valid
+  ColourGrid(const LevelGeom& g, int colour) {
+    constexpr int PPW = SmootherShape<D, K>::PPW;
+    const int half = (int)(g.ncells / 2);
+    for (int a = 0; a < D; ++a) {
+      p[a] = (colour >> a) & 1;
+      cnt[a] = half - p[a];
+    }
+    for (int a = 0; a < D; ++a)
+      if (cnt[a] <= 0) return;  // empty colour (coarsest level)
+    groups0 = (cnt[0] + PPW - 1) / PPW;
+    blocks = (long long)groups0 * cnt[1] * (D == 3 ? cnt[2] : 1);
+    constexpr long long n = 2 * K + 1;
+    const long long span = (D == 3 ? (n - 1) * g.n1d * g.n1d : 0) + (n - 1) * g.n1d + 2 * K * PPW + 1;
+    ok = blocks <= 0x7fffffffLL && span < (1LL << 31);
+  }
+};
 
 template <int D, int K, typename T, bool ADD>
 static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
-  constexpr int PPW = SmootherShape<D, K>::PPW, NT = SmootherShape<D, K>::NT;
-  const int half = (int)(g.ncells / 2);
-  int p[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-  for (int a = 0; a < D; ++a) {
-    p[a] = (colour >> a) & 1;
-    cnt[a] = half - p[a];
-  }
-  for (int a = 0; a < D; ++a)
-    if (cnt[a] <= 0) return hipSuccess;  // empty colour (coarsest level)
-  const int groups0 = (cnt[0] + PPW - 1) / PPW;
-  const long long blocks = (long long)groups0 * cnt[1] * (D == 3 ? cnt[2] : 1);
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  // the kernel addresses one workgroup's block with 32-bit offsets
-  constexpr long long n = 2 * K + 1;
-  const long long span = (D == 3 ? (n - 1) * g.n1d * g.n1d : 0) + (n - 1) * g.n1d + 2 * K * PPW + 1;
-  if (span >= (1LL << 31)) return hipErrorInvalidValue;
+  constexpr int NT = SmootherShape<D, K>::NT;
+  const ColourGrid<D, K> cg(g, colour);
+  if (!cg.ok) return hipErrorInvalidConfiguration;
+  if (cg.blocks == 0) return hipSuccess;
   // Abar_h = h^(d-2) Abar_1 ; A_j,h^{-1} = h^(2-d) A_j,1^{-1}
-  const double h = g.h;
-  const T res_scale = (T)(D == 3 ? h : 1.0);
-  const T sol_scale = (T)(D == 3 ? 1.0 / h : 1.0);
-  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, ADD>), dim3((unsigned)blocks), dim3(NT), 0, st,
-                     (const T*)b, (T*)x, g.n1d, p[0], p[1], p[2], cnt[0], cnt[1], groups0, res_scale, sol_scale);
+  const T res_scale = (T)(D == 3 ? g.h : 1.0);
+  const T sol_scale = (T)(D == 3 ? 1.0 / g.h : 1.0);
+  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, ADD>), dim3((unsigned)cg.blocks), dim3(NT), 0, st, (const T*)b,
+                     (T*)x, g.n1d, cg.p[0], cg.p[1], cg.p[2], cg.cnt[0], cg.cnt[1], cg.groups0, res_scale, sol_scale);
   return hipGetLastError();
+}
+
+template <int D, int K, typename T, bool ADD>
+static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, hipStream_t st) {
+  constexpr int NT = SmootherShape<D, K>::NT;
+  ColourPassGroup grp;
+  grp.n = 0;
+  long long total = 0;
+  auto flush = [&]() -> hipError_t {
+    if (grp.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((colour_pass_group_kernel<D, K, T, ADD>), dim3((unsigned)total), dim3(NT), 0, st, grp);
+    grp.n = 0;
+    total = 0;
+    return hipGetLastError();
+  };
+  for (int i = 0; i < nm; ++i) {
+    const ColourGrid<D, K> cg(mem[i].g, colour);
+    if (!cg.ok) return hipErrorInvalidConfiguration;
+    if (cg.blocks == 0) continue;
+    if (grp.n == kMaxGroup || total + cg.blocks > 0x7fffffffLL) {
+      hipError_t e = flush();
+      if (e != hipSuccess) return e;
+    }
+    ColourPassDesc& d = grp.e[grp.n++];
+    d.b = mem[i].b;
+    d.x = mem[i].x;
+    d.n1d = mem[i].g.n1d;
+    d.p[0] = cg.p[0];
+    d.p[1] = cg.p[1];
+    d.p[2] = cg.p[2];
+    d.cnt0 = cg.cnt[0];
+    d.cnt1 = cg.cnt[1];
+    d.groups0 = cg.groups0;
+    d.block_begin = (int)total;
+    d.res_scale = D == 3 ? mem[i].g.h : 1.0;
+    d.sol_scale = D == 3 ? 1.0 / mem[i].g.h : 1.0;
+    total += cg.blocks;
+  }
+  return flush();
 }
 
 template <int D, int K>
@@ -569,6 +663,33 @@ hipError_t launch_colour_pass(const LevelGeom& g, int prec, bool additive, int c
                               hipStream_t st) {
   return g.dim == 2 ? dispatch_k<2>(g, prec, additive, colour, b, x, st)
                     : dispatch_k<3>(g, prec, additive, colour, b, x, st);
+}
+
+template <int D, int K>
+static hipError_t group_prec(int prec, bool add, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
+  if (prec == 0)
+    return add ? launch_group<D, K, double, true>(colour, m, nm, st) : launch_group<D, K, double, false>(colour, m, nm, st);
+  return add ? launch_group<D, K, float, true>(colour, m, nm, st) : launch_group<D, K, float, false>(colour, m, nm, st);
+}
+
+template <int D>
+static hipError_t group_k(int k, int prec, bool add, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
+  switch (k) {
+    case 1: return group_prec<D, 1>(prec, add, colour, m, nm, st);
+    case 2: return group_prec<D, 2>(prec, add, colour, m, nm, st);
+    case 3: return group_prec<D, 3>(prec, add, colour, m, nm, st);
+    case 4: return group_prec<D, 4>(prec, add, colour, m, nm, st);
+    case 5: return group_prec<D, 5>(prec, add, colour, m, nm, st);
+    case 6: return group_prec<D, 6>(prec, add, colour, m, nm, st);
+    case 7: return group_prec<D, 7>(prec, add, colour, m, nm, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_colour_pass_group(int dim, int k, int prec, bool additive, int colour,
+                                    const ColourPassMember* members, int n_members, hipStream_t st) {
+  return dim == 2 ? group_k<2>(k, prec, additive, colour, members, n_members, st)
+                  : group_k<3>(k, prec, additive, colour, members, n_members, st);
 }
 
 hipError_t init_smoother_tables() {

@@ -13,7 +13,8 @@ if not torch.cuda.is_available():
 
 import paper_2405_19004_amd as vps  # noqa: E402
 
-SHAPES = [(2, 1, 7), (3, 2, 3), (2, 7, 4), (3, 4, 3), (2, 3, 6), (3, 1, 5), (3, 6, 2), (2, 5, 5)]
+SHAPES = [(2, 1, 7), (3, 2, 3), (2, 7, 4), (3, 4, 3), (2, 3, 6), (3, 1, 5), (3, 6, 2), (2, 5, 5),
+          (3, 2, 4), (2, 3, 4), (3, 4, 2)]
 
 
 def _rhs(d, k, L, seed):
@@ -58,7 +59,7 @@ def _serve(reqs, budget, max_active, mode):
 def test_results_identical_alone_and_in_the_mix(mode):
     reqs = [((d, k, L), _rhs(d, k, L, 100 + i)) for i, (d, k, L) in enumerate(SHAPES)]
     reqs += reqs[:3]  # repeated shapes reuse cached hierarchies
-    xs, stats, _ = _serve(reqs, 8 << 30, 4, mode)
+    xs, stats, _ = _serve(reqs, 8 << 30, 6, mode)
     for ((d, k, L), b), x, (done, st) in zip(reqs, xs, stats):
         print("request", d, k, L, st.iterations, st.status, flush=True)
         assert done and st.status == 0
