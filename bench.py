@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--serve", type=int, default=120, help="requests in the serving run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-table7", action="store_true",
+                    help="skip the mixed/double solves at the sizes of Table 7 (135M-721M DoFs)")
     ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only 8 FP32 and 8 FP64 colour passes on the finest level, twice (for counter runs)")
@@ -144,6 +146,61 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
             "closed_loop_p99_ms": 1e3 * q(lat0, 0.99), "arrival_rate_per_s": rate,
             "p50_ms": 1e3 * q(lat1, 0.5), "p99_ms": 1e3 * q(lat1, 0.99), "mean_ms": 1e3 * sum(lat1) / len(lat1),
             "dof_per_s": total / span1, "max_active": max_active}
+
+
+# Table 7 (3D, manufactured solution prod sin(pi x_i), residual reduction 1e-9): degree,
+# level, and the printed double / mixed L2 error, iterations and seconds (other hardware).
+TABLE7 = [(1, 9, 1.12e-06, 5, 3.391, 5, 2.385), (3, 8, 2.30e-13, 3, 3.941, 3, 2.418),
+          (7, 7, 2.89e-16, 2, 5.891, 2, 3.326)]
+
+
+def table7_run(v, torch):
+    """Solves of Table 7's three problems in both precisions: time (rhs resident, solve only),
+    CG iterations and L2 error of the discrete solution."""
+    import synth
+    rows = []
+    for k, lev, l2_paper, it64_p, t64_p, itmx_p, tmx_p in TABLE7:
+        kap, co = synth.manufactured_sine(3)
+        uc = [c / (math.pi ** 2 * sum(q * q for q in kk)) for kk, c in zip(kap, co)]
+        P = v.Problem(3, k, lev, v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY | v.VPS_FLAG_POST_SAME_ORDER)
+        b = P.rhs_sine_modes(kap, co)
+        x = P.new()
+        row = {"degree": k, "level": lev, "n_dofs": P.n(),
+               "paper": {"l2_error": l2_paper, "double": {"iterations": it64_p, "s": t64_p},
+                         "mixed": {"iterations": itmx_p, "s": tmx_p}, "solver": "GMRES"}}
+        for name, mode in (("double", v.VPS_SOLVE_FP64), ("mixed", v.VPS_SOLVE_MIXED)):
+            P.pcg_solve(b, x, 1e-9, 100, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = P.pcg_solve(b, x, 1e-9, 100, mode)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            row[name] = {"iterations": st.iterations, "s": dt, "dof_per_s": P.n() / dt,
+                         "true_rel_residual": st.true_rel_residual, "l2_error": P.l2_error_sine_modes(x, kap, uc)}
+        row["speedup"] = row["double"]["s"] / row["mixed"]["s"]
+        del b, x
+        P.close()
+        torch.cuda.empty_cache()
+        rows.append(row)
+    return rows
+
+
+def fmg_run(v, torch, P, kap, co):
+    """Full multigrid on the bench problem (right-hand side on every level), both precisions."""
+    res = {}
+    for name, dt_, eps in (("fp64", torch.float64, 1e-9), ("fp32", torch.float32, 1e-4)):
+        bl = [P.rhs_sine_modes(kap, co, level=l, dtype=dt_) for l in range(1, P.L + 1)]
+        x = P.new(dt_)
+        P.fmg_solve(bl, x, eps=eps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            _, st = P.fmg_solve(bl, x, eps=eps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / 3
+        res[name] = {"eps": eps, "vcycles_after_nested_iteration": st.iterations, "rel_residual": st.rel_residual,
+                     "ms": ms, "dof_per_s": P.n() / (ms / 1e3)}
+    return res
 
 
 def cpu_baseline(N, vcycles_per_solve):
@@ -273,6 +330,7 @@ def main():
         per[name] = {"smoothing_step_ms": 1e3 * t_s, "smoother_dof_per_s": N / t_s,
                      "vcycle_ms": 1e3 * t_v, "vcycle_dof_per_s": N / t_v}
     out["smoother_vcycle"] = per
+    out["fmg"] = fmg_run(v, torch, P, kap, co)
 
     # roofline of the dominant kernel: the FP32 colour pass on the finest level
     info = P.info()
@@ -303,6 +361,8 @@ def main():
 
     if a.serve > 0:
         out["serving"] = serving_run(v, a.serve)
+    if not a.no_table7:
+        out["table7"] = table7_run(v, torch)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, its[-1] + 1)
     print(json.dumps(out))

@@ -56,7 +56,7 @@ enum vps_status {
 };
 
 enum vps_prec { VPS_FP64 = 0, VPS_FP32 = 1 };
-enum vps_smooth { VPS_MULTIPLICATIVE = 0, VPS_ADDITIVE = 1 };
+enum vps_smooth { VPS_MULTIPLICATIVE = 0, VPS_ADDITIVE = 1, VPS_MULTIPLICATIVE_BOUNDARY = 2 };
 enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
 
 /* vps_create flags */
@@ -66,6 +66,8 @@ enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
 #define VPS_FLAG_POST_SAME_ORDER 0x8u /* post-smoothing colours ascending (Alg. 1 read literally; the
                                          V-cycle is then not symmetric and vps_pcg_solve uses the flexible
                                          beta in both modes).  Default: descending (symmetric V-cycle). */
+#define VPS_FLAG_BOUNDARY_SMOOTHER 0x10u /* V-cycles smooth with the "Boundary" kernel
+                                            (VPS_MULTIPLICATIVE_BOUNDARY below; Sec. 4.1.3) */
 
 typedef struct vps_problem vps_problem;
 
@@ -121,7 +123,10 @@ int vps_residual(vps_problem* p, int level, int prec, const void* b, const void*
  *   x_j^I += A_j^{-1}(b_j^I - Abar_j x_j) with the localised residual of Sec. 2.2.
  * VPS_ADDITIVE: x += sum_j R_j^T A_j^{-1} R_j b (b is a residual; undamped; the
  *   colours only order the accumulation, the result does not depend on them
- *   beyond rounding). */
+ *   beyond rounding).
+ * VPS_MULTIPLICATIVE_BOUNDARY: the multiplicative smoother computed as in Sec. 4.1.3
+ *   (eq:A_ib_2d/3d): since A_j^{-1} is exact, x_j^I <- A_j^{-1}(b_j^I - A^{IB} x_j^B); the old
+ *   interior values are never read.  Equal to VPS_MULTIPLICATIVE up to rounding. */
 int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int reverse_colors, const void* b, void* x);
 
 /* One colour of Alg. 3 (mode as above) on `level`; color in 0..2^dim-1 where the colour of the
@@ -154,10 +159,30 @@ int vps_vcycle(vps_problem* p, int prec, const void* b, void* x);
 int vps_pcg_solve(vps_problem* p, int solve_mode, const double* b, double* x, double rtol, int maxit,
                   vps_solve_stats_t* stats);
 
+/* Full multigrid (Alg. 2).  b_levels[l-1] (l = 1..L): device right-hand side of level l in
+ * precision prec (boundary entries ignored); x: level-L result in prec (overwritten).
+ * Level 1 is solved exactly, each finer level starts from the prolongated coarser solution
+ * and takes one V-cycle; then V-cycles on level L repeat until ||b_L - A x||_2 <= eps ||b_L||_2
+ * (interior norms) or maxit of them were taken.  stats->iterations counts those repeated
+ * V-cycles (the n of Tables 1-2); rel_residual = true_rel_residual = the final ratio.
+ * The colour order of the V-cycles follows VPS_FLAG_POST_SAME_ORDER.  Needs the matching
+ * hierarchy flag and the solver vectors; synchronises once per V-cycle on level L.
+ * Returns VPS_OK, VPS_ENOCONV or VPS_ENOTFINITE (stats filled in every case). */
+int vps_fmg_solve(vps_problem* p, int prec, const void* const* b_levels, void* x, double eps, int maxit,
+                  vps_solve_stats_t* stats);
+
 /* b_i = int f phi_i for f = sum_m coef[m] prod_a sin(pi kappa[m*dim + a] x_a) on `level`
  * ((k+1)-point Gauss per cell direction; eq:matrix-def).  kappa, coef: host arrays. */
 int vps_rhs_sine_modes(vps_problem* p, int level, int prec, int n_modes, const int* kappa,
                        const double* coef, void* b);
+
+/* *err = || u - u_h ||_{L2(Omega)} for u = sum_m ucoef[m] prod_a sin(pi kappa[m*dim + a] x_a)
+ * and u_h the FP64 finite element function with nodal values x (device, full level-`level`
+ * grid), integrated cellwise with nq^d Gauss points (nq = 0: k+1; at most 16); the error
+ * measure of the convergence study (Sec. 4.2, Table 7).  kappa, ucoef: host arrays.
+ * Deterministic; synchronises the problem's stream. */
+int vps_l2_error_sine_modes(vps_problem* p, int level, int n_modes, const int* kappa, const double* ucoef,
+                            int nq, const double* x, double* err);
 
 /* Wait for all work enqueued on the problem's stream. */
 int vps_synchronize(vps_problem* p);

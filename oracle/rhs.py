@@ -41,6 +41,24 @@ def rhs_sine_modes(d, k, level, kappas, coefs):
     return b
 
 
+def rhs_constant(d, k, level):
+    """b for f = 1 (the right-hand side of the FMG tests, Sec. 4.1): Kronecker product of the
+    1D load vector of 1, whose entries are the row sums of h * Mhat over the cells."""
+    _, Mhat = basis.reference_matrices(k)
+    h = mesh.mesh_size(level)
+    g = np.zeros(mesh.n1d(k, level))
+    for c in range(2 ** level):
+        g[k * c:k * c + k + 1] += h * Mhat.sum(1)
+    B = np.ones((1,) * d)
+    for a in range(d):
+        shape = [1] * d
+        shape[d - 1 - a] = len(g)
+        B = B * g.reshape(shape)
+    b = B.reshape(-1)
+    b[mesh.boundary_mask(d, k, level)] = 0
+    return b
+
+
 def rhs_bruteforce(d, k, level, f):
     """b_i = int f phi_i by d-dim cellwise Gauss quadrature, point by point (tiny meshes; pins)."""
     import itertools

@@ -116,6 +116,66 @@ def colour_pass(d, k, level, b, x, colour, lu=None):
     return x
 
 
+def patch_1d_matrices(k, h):
+    """1D patch matrices on the 2k+1 nodes of two cells of size h: stiffness (Ahat/h) and
+    mass (h*Mhat) assembled over both cells."""
+    Ahat, Mhat = basis.reference_matrices(k)
+    n = 2 * k + 1
+    A, M = np.zeros((n, n)), np.zeros((n, n))
+    for c in (0, 1):
+        s = slice(k * c, k * c + k + 1)
+        A[s, s] += Ahat / h
+        M[s, s] += h * Mhat
+    return A, M
+
+
+def a_ib_kronecker(d, k, h):
+    """A^{IB} of a vertex patch from the Kronecker blocks of eq:A_ib_2d / eq:A_ib_3d.
+
+    The boundary closure nodes fall into d groups: group g holds the nodes whose axis-g index
+    is on the patch boundary, whose higher axes are interior and whose lower axes are
+    arbitrary.  On group g every direction term of the operator is a Kronecker product of
+    1D blocks: interior rows throughout, boundary columns on axis g, all columns below g and
+    interior columns above g.  Returns (A^{IB}, closure-local ids of its columns).
+    """
+    A1, M1 = patch_1d_matrices(k, h)
+    n = 2 * k + 1
+    inner, bnd, every = np.arange(1, n - 1), np.array([0, n - 1]), np.arange(n)
+    blocks, cols = [], []
+    for g in range(d):
+        colsets = [every if a < g else (bnd if a == g else inner) for a in range(d)]
+        total = 0.0
+        for direction in range(d):
+            mats = [(A1 if a == direction else M1)[np.ix_(inner, colsets[a])] for a in range(d)]
+            total = total + basis._kron_axes(mats)
+        blocks.append(total)
+        ids = np.zeros([len(colsets[a]) for a in reversed(range(d))], dtype=np.int64)
+        for a in range(d):
+            shape = [1] * d
+            shape[d - 1 - a] = len(colsets[a])
+            ids = ids + colsets[a].reshape(shape) * n ** a
+        cols.append(ids.reshape(-1))
+    return np.hstack(blocks), np.concatenate(cols)
+
+
+def colour_pass_boundary(d, k, level, b, x, colour):
+    """One colour of Alg. 3 in the form of Sec. 4.1.3: x_j^I <- A_j^{-1}(b_j^I - A^{IB} x_j^B).
+
+    Reads only the boundary nodes of each patch closure (Dirichlet nodes count as 0)."""
+    verts = mesh.patches_of_colour(d, level, colour)
+    x = np.asarray(x, dtype=np.float64).copy()
+    if len(verts) == 0:
+        return x
+    A_ib, bcols = a_ib_kronecker(d, k, mesh.mesh_size(level))
+    xz = x.copy()
+    xz[mesh.boundary_mask(d, k, level)] = 0.0
+    C = np.stack([mesh.patch_closure_ids(d, k, level, v) for v in verts])
+    I = np.stack([mesh.patch_interior_ids(d, k, level, v) for v in verts])
+    rhs = np.asarray(b)[I] - xz[C[:, bcols]] @ A_ib.T
+    x[I] = sla.lu_solve(_patch_lu(d, k, level), rhs.T).T
+    return x
+
+
 def multiplicative(d, k, level, b, x, reverse=False):
     """Colourised multiplicative vertex-patch smoother S_l(x, b) (Alg. 3).
 

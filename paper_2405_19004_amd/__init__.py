@@ -16,9 +16,10 @@ LIB_PATH = os.environ.get("VPS_LIB") or os.path.join(_HERE, "libvps.so")
 
 VPS_OK, VPS_EINVAL, VPS_ENOMEM, VPS_EHIP, VPS_ENOCONV, VPS_EBREAKDOWN, VPS_ENOTFINITE, VPS_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 VPS_FP64, VPS_FP32 = 0, 1
-VPS_MULTIPLICATIVE, VPS_ADDITIVE = 0, 1
+VPS_MULTIPLICATIVE, VPS_ADDITIVE, VPS_MULTIPLICATIVE_BOUNDARY = 0, 1, 2
 VPS_SOLVE_FP64, VPS_SOLVE_MIXED = 0, 1
 VPS_FLAG_FP64_HIERARCHY, VPS_FLAG_FP32_HIERARCHY, VPS_FLAG_NO_SOLVER, VPS_FLAG_POST_SAME_ORDER = 0x1, 0x2, 0x4, 0x8
+VPS_FLAG_BOUNDARY_SMOOTHER = 0x10
 
 _STATUS_NAMES = {0: "VPS_OK", -1: "VPS_EINVAL", -2: "VPS_ENOMEM", -3: "VPS_EHIP", -4: "VPS_ENOCONV",
                  -5: "VPS_EBREAKDOWN", -6: "VPS_ENOTFINITE", -7: "VPS_EBUSY"}
@@ -62,6 +63,9 @@ _SIGS = {
     "vps_vcycle": (_I, [_P, _I, _P, _P]),
     "vps_pcg_solve": (_I, [_P, _I, _P, _P, ctypes.c_double, _I, ctypes.POINTER(SolveStats)]),
     "vps_rhs_sine_modes": (_I, [_P, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double), _P]),
+    "vps_fmg_solve": (_I, [_P, _I, ctypes.POINTER(_P), _P, ctypes.c_double, _I, ctypes.POINTER(SolveStats)]),
+    "vps_l2_error_sine_modes": (_I, [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double), _I, _P,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "vps_synchronize": (_I, [_P]),
     "vps_last_error": (ctypes.c_char_p, []),
     "vps_host_table": (_I, [_I, _I, ctypes.POINTER(ctypes.c_double), _I, ctypes.POINTER(_I)]),
@@ -188,11 +192,29 @@ def vps_pcg_solve(h, solve_mode, b_ptr, x_ptr, rtol, maxit):
     return st
 
 
+def vps_fmg_solve(h, prec, b_ptrs, x_ptr, eps, maxit):
+    st = SolveStats()
+    arr = (_P * len(b_ptrs))(*b_ptrs)
+    status = lib().vps_fmg_solve(h, prec, arr, x_ptr, eps, maxit, ctypes.byref(st))
+    if status not in (VPS_OK, VPS_ENOCONV):
+        raise VpsError(status, last_error())
+    return st
+
+
 def vps_rhs_sine_modes(h, level, prec, kappas, coefs, b_ptr):
     flat = [int(v) for kap in kappas for v in kap]
     kap = (_I * max(len(flat), 1))(*flat)
     co = (ctypes.c_double * max(len(coefs), 1))(*[float(c) for c in coefs])
     return _call("vps_rhs_sine_modes", h, level, prec, len(coefs), kap, co, b_ptr)
+
+
+def vps_l2_error_sine_modes(h, level, kappas, ucoefs, nq, x_ptr):
+    flat = [int(v) for kap in kappas for v in kap]
+    kap = (_I * max(len(flat), 1))(*flat)
+    co = (ctypes.c_double * max(len(ucoefs), 1))(*[float(c) for c in ucoefs])
+    err = ctypes.c_double()
+    _call("vps_l2_error_sine_modes", h, level, len(ucoefs), kap, co, nq, x_ptr, ctypes.byref(err))
+    return err.value
 
 
 def vps_synchronize(h):
@@ -365,6 +387,22 @@ class Problem:
         st = vps_pcg_solve(self.h, mode, b.data_ptr(), x.data_ptr(), rtol, maxit)
         return x, st
 
+    def fmg_solve(self, b_levels, x=None, eps=1e-9, maxit=50):
+        """Full multigrid; b_levels[l-1] is the right-hand side of level l (l = 1..L), one dtype."""
+        if len(b_levels) != self.L:
+            raise ValueError("need one right-hand side per level (%d)" % self.L)
+        prec = None
+        for lvl, b in enumerate(b_levels, start=1):
+            p = self._chk(lvl, b)
+            if prec is not None and p != prec:
+                raise TypeError("all levels must share a dtype")
+            prec = p
+        x = self.new(b_levels[0].dtype) if x is None else x
+        if self._chk(self.L, x) != prec:
+            raise TypeError("x must have the right-hand sides' dtype")
+        st = vps_fmg_solve(self.h, prec, [b.data_ptr() for b in b_levels], x.data_ptr(), eps, maxit)
+        return x, st
+
     def rhs_sine_modes(self, kappas, coefs, b=None, level=None, dtype=None):
         level = self.L if level is None else level
         b = self.new(dtype, level) if b is None else b
@@ -374,6 +412,17 @@ class Problem:
         prec = self._chk(level, b)
         vps_rhs_sine_modes(self.h, level, prec, kappas, coefs, b.data_ptr())
         return b
+
+    def l2_error_sine_modes(self, x, kappas, ucoefs, level=None, nq=0):
+        """L2 error of the FP64 nodal vector x against sum ucoefs[m] prod_a sin(pi kappas[m][a] x_a)."""
+        level = self.L if level is None else level
+        for kap in kappas:
+            if len(kap) != self.dim:
+                raise ValueError("each mode needs %d wave numbers" % self.dim)
+        prec = self._chk(level, x)
+        if prec != VPS_FP64:
+            raise ValueError("x must be FP64")
+        return vps_l2_error_sine_modes(self.h, level, kappas, ucoefs, nq, x.data_ptr())
 
     def synchronize(self):
         vps_synchronize(self.h)

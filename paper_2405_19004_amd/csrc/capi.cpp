@@ -204,7 +204,8 @@ int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int revers
   return guarded([&]() -> int {
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
-    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE) return fail(VPS_EINVAL, "bad smoother mode");
+    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY)
+      return fail(VPS_EINVAL, "bad smoother mode");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");
     return from(vps::smoother(p->impl, level, prec, mode, reverse_colors != 0, b, x));
   });
@@ -214,7 +215,8 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
   return guarded([&]() -> int {
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
-    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE) return fail(VPS_EINVAL, "bad smoother mode");
+    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY)
+      return fail(VPS_EINVAL, "bad smoother mode");
     if (color < 0 || color >= (1 << p->impl->dim)) return fail(VPS_EINVAL, "color out of range");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");
     return from(vps::colour_pass(p->impl, level, prec, mode, color, b, x));
@@ -286,6 +288,30 @@ int vps_pcg_solve(vps_problem* p, int solve_mode, const double* b, double* x, do
   });
 }
 
+int vps_fmg_solve(vps_problem* p, int prec, const void* const* b_levels, void* x, double eps, int maxit,
+                  vps_solve_stats_t* stats) {
+  return guarded([&]() -> int {
+    if (!p || !p->impl) return fail(VPS_EINVAL, "null problem");
+    if (int e = check_prec(prec)) return e;
+    if (!b_levels || !x) return fail(VPS_EINVAL, "null vector");
+    for (int l = 0; l < p->impl->L; ++l)
+      if (!b_levels[l]) return fail(VPS_EINVAL, "null right-hand side on a level");
+    if (!(eps > 0.0) || maxit < 0) return fail(VPS_EINVAL, "eps must be > 0 and maxit >= 0");
+    vps::SolveStats st;
+    vps::Status s = vps::fmg(p->impl, prec, b_levels, x, eps, maxit, &st);
+    if (s.code) return from(s);
+    if (stats) {
+      stats->iterations = st.iterations;
+      stats->rel_residual = st.rel_residual;
+      stats->true_rel_residual = st.true_rel_residual;
+      stats->status = st.status;
+    }
+    if (st.status != 0)
+      return fail(st.status, st.status == VPS_ENOCONV ? "V-cycle limit reached" : "non-finite right-hand side or residual");
+    return VPS_OK;
+  });
+}
+
 int vps_rhs_sine_modes(vps_problem* p, int level, int prec, int n_modes, const int* kappa, const double* coef,
                        void* b) {
   return guarded([&]() -> int {
@@ -331,6 +357,66 @@ int vps_rhs_sine_modes(vps_problem* p, int level, int prec, int n_modes, const i
     if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
     cleanup();
     return e == hipSuccess ? VPS_OK : fail(VPS_EHIP, std::string("rhs: ") + hipGetErrorString(e));
+  });
+}
+
+int vps_l2_error_sine_modes(vps_problem* p, int level, int n_modes, const int* kappa, const double* ucoef, int nq,
+                            const double* x, double* err) {
+  return guarded([&]() -> int {
+    if (int e = check_level(p, level, 1)) return e;
+    if (n_modes < 0 || (n_modes > 0 && (!kappa || !ucoef)) || !x || !err) return fail(VPS_EINVAL, "bad arguments");
+    const vps::Problem& P = *p->impl;
+    const int k = P.k, np = k + 1;
+    if (nq == 0) nq = np;
+    if (nq < 1 || nq > 16) return fail(VPS_EINVAL, "nq must be 0 (k+1) or in 1..16");
+    const vps::LevelGeom& g = P.geom(level);
+    const vps::Tables1D& t = vps::tables_for_degree(k);
+    const double pi = std::acos(-1.0);
+    std::vector<double> xq, wq;
+    vps::gauss_legendre(nq, xq, wq);
+    std::vector<double> V((size_t)nq * np);  // V[q*np + i] = phi_i(xq_q)
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < np; ++i) V[(size_t)q * np + i] = vps::lagrange(t.gll, i, xq[q]);
+    const size_t na = (size_t)g.ncells * nq;
+    std::vector<double> S((size_t)std::max(n_modes, 1) * P.dim * na, 0.0);
+    for (int m = 0; m < n_modes; ++m)
+      for (int a = 0; a < P.dim; ++a) {
+        const double kap = kappa[m * P.dim + a];
+        double* sv = &S[((size_t)m * P.dim + a) * na];
+        for (long long c = 0; c < g.ncells; ++c)
+          for (int q = 0; q < nq; ++q) sv[c * nq + q] = std::sin(pi * kap * (c + xq[q]) * g.h);
+      }
+    const int nparts = 4096;
+    const size_t bytes[5] = {V.size() * 8, wq.size() * 8, S.size() * 8, (size_t)std::max(n_modes, 1) * 8,
+                             (size_t)nparts * 8};
+    void* d[5] = {};
+    auto cleanup = [&] {
+      for (void* q : d)
+        if (q) (void)hipFree(q);
+    };
+    for (int i = 0; i < 5; ++i)
+      if (hipMalloc(&d[i], bytes[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(VPS_ENOMEM, "L2 error scratch allocation failed");
+      }
+    hipError_t e = hipMemcpyAsync(d[0], V.data(), bytes[0], hipMemcpyHostToDevice, P.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d[1], wq.data(), bytes[1], hipMemcpyHostToDevice, P.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d[2], S.data(), bytes[2], hipMemcpyHostToDevice, P.stream);
+    if (e == hipSuccess && n_modes > 0)
+      e = hipMemcpyAsync(d[3], ucoef, (size_t)n_modes * 8, hipMemcpyHostToDevice, P.stream);
+    if (e == hipSuccess)
+      e = vps::launch_l2_error(g, x, (const double*)d[0], (const double*)d[1], (const double*)d[2],
+                               (const double*)d[3], n_modes, nq, (double*)d[4], nparts, P.stream);
+    std::vector<double> part(nparts);
+    if (e == hipSuccess) e = hipMemcpyAsync(part.data(), d[4], bytes[4], hipMemcpyDeviceToHost, P.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P.stream);
+    cleanup();
+    if (e != hipSuccess) return fail(VPS_EHIP, std::string("L2 error: ") + hipGetErrorString(e));
+    double sum = 0.0;
+    for (double v : part) sum += v;
+    *err = std::sqrt(sum);
+    return VPS_OK;
   });
 }
 

@@ -584,6 +584,69 @@ __global__ void rhs_separable_kernel(T* __restrict__ b, const double* __restrict
   b[idx] = (T)s;
 }
 
+// ------------------------------------------------------------------ L2 error
+
+// Squared L2 error of u_h (nodal values x) against u = sum_m uc[m] prod_a sin(pi kappa_ma x_a)
+// with cellwise nq^d Gauss points.  One thread per (cell, q2, q1) quadrature line: it contracts
+// the (k+1)^d nodal values of its cell over axes 2 and 1 (V[q*(k+1) + i] = phi_i(xi_q)), then
+// evaluates the nq points of the line along axis 0.  u comes from per-axis sine tables
+// S[(m*dim + a)*ncells*nq + c*nq + q].  Block partial sums in a fixed order.
+template <int K>
+__global__ void __launch_bounds__(256) l2_error_kernel(const double* __restrict__ x, const double* __restrict__ V,
+                                                       const double* __restrict__ wq, const double* __restrict__ S,
+                                                       const double* __restrict__ uc, int nmodes, int dim, int nq,
+                                                       long long ncells, long long n1d, long long nlines,
+                                                       double cellvol, double* __restrict__ partial) {
+  constexpr int NP = K + 1;
+  __shared__ double red[256];
+  double acc = 0.0;
+  const long long nql = dim == 2 ? nq : (long long)nq * nq;  // lines per cell
+  const long long na = ncells * nq;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nlines; t += (long long)gridDim.x * blockDim.x) {
+    const long long cell = t / nql;
+    const int li = (int)(t - cell * nql);
+    const int q1 = li % nq, q2 = dim == 3 ? li / nq : 0;
+    const long long c0 = cell % ncells, c1 = (cell / ncells) % ncells, c2 = dim == 3 ? cell / (ncells * ncells) : 0;
+    const long long base = (dim == 3 ? (long long)K * c2 * n1d * n1d : 0) + (long long)K * c1 * n1d + (long long)K * c0;
+    double line[NP];
+#pragma unroll
+    for (int i0 = 0; i0 < NP; ++i0) line[i0] = 0.0;
+    for (int i2 = 0; i2 < (dim == 3 ? NP : 1); ++i2) {
+      const double v2 = dim == 3 ? V[q2 * NP + i2] : 1.0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) {
+        const double v21 = v2 * V[q1 * NP + i1];
+        const double* row = x + base + (long long)i2 * n1d * n1d + (long long)i1 * n1d;
+#pragma unroll
+        for (int i0 = 0; i0 < NP; ++i0) line[i0] = fma(v21, row[i0], line[i0]);
+      }
+    }
+    double w12 = wq[q1] * cellvol;
+    if (dim == 3) w12 *= wq[q2];
+    for (int q0 = 0; q0 < nq; ++q0) {
+      double uh = 0.0;
+#pragma unroll
+      for (int i0 = 0; i0 < NP; ++i0) uh = fma(V[q0 * NP + i0], line[i0], uh);
+      double u = 0.0;
+      for (int m = 0; m < nmodes; ++m) {
+        const double* Sm = S + (long long)m * dim * na;
+        double v = uc[m] * Sm[c0 * nq + q0] * Sm[na + c1 * nq + q1];
+        if (dim == 3) v *= Sm[2 * na + c2 * nq + q2];
+        u += v;
+      }
+      const double e = u - uh;
+      acc = fma(w12 * wq[q0] * e, e, acc);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // ------------------------------------------------------------------ launchers
 
 namespace {
@@ -717,6 +780,25 @@ hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const 
   else
     hipLaunchKernelGGL(rhs_separable_kernel<float>, dim3(blocks), dim3(256), 0, st, (float*)b, G, coef, nterms, g.dim,
                        g.n1d, ntot);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_error(const LevelGeom& g, const double* x, const double* V, const double* wq, const double* S,
+                           const double* uc, int nmodes, int nq, double* partial, int nparts, hipStream_t st) {
+  const long long ncd = g.dim == 2 ? g.ncells * g.ncells : g.ncells * g.ncells * g.ncells;
+  const long long nlines = ncd * (g.dim == 2 ? nq : nq * nq);
+  const double cellvol = g.dim == 2 ? g.h * g.h : g.h * g.h * g.h;
+  switch (g.k) {
+#define VPS_L2(KK)                                                                                                 \
+  case KK:                                                                                                         \
+    hipLaunchKernelGGL(l2_error_kernel<KK>, dim3(nparts), dim3(256), 0, st, x, V, wq, S, uc, nmodes, g.dim, nq,    \
+                       g.ncells, g.n1d, nlines, cellvol, partial);                                                   \
+    break;
+    VPS_L2(1) VPS_L2(2) VPS_L2(3) VPS_L2(4) VPS_L2(5) VPS_L2(6) VPS_L2(7)
+#undef VPS_L2
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

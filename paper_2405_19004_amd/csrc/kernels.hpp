@@ -25,6 +25,10 @@ enum : int {
 
 hipError_t init_smoother_tables();
 
+// Colour-pass kernels: multiplicative (residual, then x^I += A_j^{-1} r), additive
+// (x^I += A_j^{-1} b^I) and Boundary (x^I = A_j^{-1} (b^I - A^{IB} x^B), x^I never read).
+enum { kModeMultiplicative = 0, kModeAdditive = 1, kModeBoundary = 2 };
+
 // One member of a packed colour-pass launch (see launch_colour_pass_group).
 struct ColourPassDesc {
   const void* b;
@@ -47,12 +51,12 @@ struct ColourPassMember {
 };
 // Colour `colour` on every member (same dim, degree and precision; any levels) with one launch
 // per kMaxGroup members.  Each member's arithmetic is exactly that of launch_colour_pass.
-hipError_t launch_colour_pass_group(int dim, int k, int prec, bool additive, int colour,
+hipError_t launch_colour_pass_group(int dim, int k, int prec, int mode, int colour,
                                     const ColourPassMember* members, int n_members, hipStream_t st);
 hipError_t init_grid_tables();
 
 // smoother.hip
-hipError_t launch_colour_pass(const LevelGeom& g, int prec, bool additive, int colour, const void* b, void* x,
+hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour, const void* b, void* x,
                               hipStream_t st);
 
 // grid.hip (interior outputs only)
@@ -68,6 +72,10 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);
 hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const double* G, const double* coef, void* b,
                                 hipStream_t st);
+
+// Partial sums (nparts doubles) of the squared L2 error, cellwise nq-point Gauss (see grid.hip).
+hipError_t launch_l2_error(const LevelGeom& g, const double* x, const double* V, const double* wq, const double* S,
+                           const double* uc, int nmodes, int nq, double* partial, int nparts, hipStream_t st);
 
 // vector.hip
 int reduction_parts();  // partial slots the reductions use (pairs: 2x this many doubles)

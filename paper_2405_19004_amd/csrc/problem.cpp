@@ -22,7 +22,8 @@
 
 namespace vps {
 
-enum { kMult = 0, kAdd = 1 };
+// Kernel mode of the V-cycle smoothing steps.
+inline int vcycle_mode(const Problem* p) { return p->boundary_smoother ? kModeBoundary : kModeMultiplicative; }
 
 long long level_nodes(int dim, int k, int level) {
   long long n = (long long)k * (1LL << level) + 1;
@@ -119,6 +120,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   p->flags = flags;
   p->stream = st;
   p->post_same_order = flags & 0x8u;
+  p->boundary_smoother = flags & 0x10u;
   p->lv.resize(L + 1);
   Plan pl = plan(dim, k, L, flags);
   std::vector<void*> ptrs;
@@ -187,7 +189,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
 // ------------------------------------------------------------------ smoothing
 
 Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x) {
-  VPS_HIP(launch_colour_pass(p->geom(level), prec, mode == kAdd, colour, b, x, p->stream));
+  VPS_HIP(launch_colour_pass(p->geom(level), prec, mode, colour, b, x, p->stream));
   return Status::ok();
 }
 
@@ -205,40 +207,126 @@ Status coarse_solve(Problem* p, int prec, const void* b, void* x) {
   const long long N = p->lv[1].N;
   if (prec == 0) {
     VPS_HIP(launch_fill(0, x, N, 0.0, p->stream));
-    VPS_HIP(launch_colour_pass(g, 0, false, 0, b, x, p->stream));
+    VPS_HIP(launch_colour_pass(g, 0, kModeMultiplicative, 0, b, x, p->stream));
     return Status::ok();
   }
   if (!p->c64_b) return Status{-1, "FP32 coarse solve needs the FP32 hierarchy"};
   VPS_HIP(launch_cast(1, b, p->c64_b, N, p->stream));
   VPS_HIP(launch_fill(0, p->c64_x, N, 0.0, p->stream));
-  VPS_HIP(launch_colour_pass(g, 0, false, 0, p->c64_b, p->c64_x, p->stream));
+  VPS_HIP(launch_colour_pass(g, 0, kModeMultiplicative, 0, p->c64_b, p->c64_x, p->stream));
   VPS_HIP(launch_cast(0, p->c64_x, x, N, p->stream));
   return Status::ok();
 }
 
-Status vcycle(Problem* p, int prec, const void* bL, void* xL) {
+Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT) {
   if (!p->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
-  const int L = p->L;
-  if (L == 1) return coarse_solve(p, prec, bL, xL);
+  if (top == 1) return coarse_solve(p, prec, bT, xT);
   const bool post_rev = !p->post_same_order;
   // descend
-  for (int lvl = L; lvl >= 2; --lvl) {
-    const void* b = lvl == L ? bL : p->lv[lvl].b[prec];
-    void* x = lvl == L ? xL : p->lv[lvl].x[prec];
-    if (lvl < L) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
-    VPS_TRY(smoother(p, lvl, prec, kMult, false, b, x));
+  for (int lvl = top; lvl >= 2; --lvl) {
+    const void* b = lvl == top ? bT : p->lv[lvl].b[prec];
+    void* x = lvl == top ? xT : p->lv[lvl].x[prec];
+    if (lvl < top) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
+    VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), false, b, x));
     VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
     VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
                             p->lv[lvl].t2[prec], p->stream));
   }
   VPS_TRY(coarse_solve(p, prec, p->lv[1].b[prec], p->lv[1].x[prec]));
   // ascend
-  for (int lvl = 2; lvl <= L; ++lvl) {
-    const void* b = lvl == L ? bL : p->lv[lvl].b[prec];
-    void* x = lvl == L ? xL : p->lv[lvl].x[prec];
+  for (int lvl = 2; lvl <= top; ++lvl) {
+    const void* b = lvl == top ? bT : p->lv[lvl].b[prec];
+    void* x = lvl == top ? xT : p->lv[lvl].x[prec];
     VPS_HIP(launch_prolongate_add(p->geom(lvl), prec, p->lv[lvl - 1].x[prec], x, p->stream));
-    VPS_TRY(smoother(p, lvl, prec, kMult, post_rev, b, x));
+    VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), post_rev, b, x));
   }
+  return Status::ok();
+}
+
+Status vcycle(Problem* p, int prec, const void* bL, void* xL) { return vcycle_top(p, prec, p->L, bL, xL); }
+
+// ------------------------------------------------------------------------ FMG
+
+namespace {
+
+// *out_slot <- ||v||^2 over the interior nodes of the finest level (v in `prec`); the FP64 copy
+// goes to p->q.  Sets p->bad on a non-finite entry.
+Status interior_norm2(Problem* p, int prec, const void* v, double* out_slot) {
+  const LevelGeom& g = p->geom(p->L);
+  const double* src = static_cast<const double*>(v);
+  if (prec == 1) {
+    VPS_HIP(launch_cast(1, v, p->z, p->lv[p->L].N, p->stream));
+    src = p->z;
+  }
+  VPS_HIP(launch_copy_interior_norm(p->dim, g.n1d, src, p->q, p->partial, out_slot, p->bad, p->stream));
+  return Status::ok();
+}
+
+// *out_slot <- ||b - A x||^2 on the finest level (residual formed in `prec`).  The residual
+// buffers keep zero boundary entries: the operator kernel writes interior nodes only.
+Status residual_norm2(Problem* p, int prec, const void* b, const void* x, double* out_slot) {
+  const LevelGeom& g = p->geom(p->L);
+  const long long N = p->lv[p->L].N;
+  if (prec == 0) {
+    VPS_HIP(launch_operator(g, 0, x, b, p->q, p->stream));
+  } else {
+    void* r32 = p->lv[p->L].r[1];
+    if (!r32) {  // single-level hierarchy: FP32 residual in the front half of z
+      r32 = p->z;
+      VPS_HIP(launch_fill(1, r32, N, 0.0, p->stream));
+    }
+    VPS_HIP(launch_operator(g, 1, x, b, r32, p->stream));
+    VPS_HIP(launch_cast(1, r32, p->q, N, p->stream));
+  }
+  VPS_HIP(launch_dot2(p->q, p->q, nullptr, nullptr, N, p->partial, out_slot, p->stream));
+  return Status::ok();
+}
+
+Status fetch_scalars(Problem* p) {
+  VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  VPS_HIP(hipMemcpyAsync(p->host_bad, p->bad, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  VPS_HIP(hipStreamSynchronize(p->stream));
+  return Status::ok();
+}
+
+}  // namespace
+
+Status fmg(Problem* p, int prec, const void* const* b_levels, void* x, double eps, int maxit, SolveStats* out) {
+  if (!p->r) return Status{-1, "FMG needs the solver vectors (problem created without them)"};
+  if (!p->has(prec)) return Status{-1, "FMG precision was not requested at creation"};
+  const int L = p->L;
+  SolveStats st;
+  VPS_HIP(hipMemsetAsync(p->bad, 0, sizeof(int), p->stream));
+  VPS_TRY(interior_norm2(p, prec, b_levels[L - 1], p->sc + kScBB));
+  // nested iteration: exact solve on level 1, then one V-cycle per level from the prolongated
+  // coarser solution
+  auto level_x = [&](int lvl) -> void* { return lvl == L ? x : p->lv[lvl].x[prec]; };
+  VPS_TRY(coarse_solve(p, prec, b_levels[0], level_x(1)));
+  for (int lvl = 2; lvl <= L; ++lvl) {
+    VPS_HIP(launch_fill(prec, level_x(lvl), p->lv[lvl].N, 0.0, p->stream));
+    VPS_HIP(launch_prolongate_add(p->geom(lvl), prec, level_x(lvl - 1), level_x(lvl), p->stream));
+    VPS_TRY(vcycle_top(p, prec, lvl, b_levels[lvl - 1], level_x(lvl)));
+  }
+  VPS_TRY(residual_norm2(p, prec, b_levels[L - 1], x, p->sc + kScTrue));
+  VPS_TRY(fetch_scalars(p));
+  const double d0 = std::sqrt(p->host_sc[kScBB]);
+  if (*p->host_bad || !std::isfinite(d0)) {
+    st.status = -6;
+    if (out) *out = st;
+    return Status::ok();
+  }
+  double delta = std::sqrt(p->host_sc[kScTrue]);
+  // further V-cycles on the finest level until the residual has dropped by eps
+  while (std::isfinite(delta) && delta > eps * d0 && st.iterations < maxit) {
+    VPS_TRY(vcycle_top(p, prec, L, b_levels[L - 1], x));
+    VPS_TRY(residual_norm2(p, prec, b_levels[L - 1], x, p->sc + kScTrue));
+    VPS_TRY(fetch_scalars(p));
+    delta = std::sqrt(p->host_sc[kScTrue]);
+    st.iterations += 1;
+  }
+  st.rel_residual = st.true_rel_residual = d0 > 0.0 ? delta / d0 : delta;
+  st.status = !std::isfinite(delta) ? -6 : delta > eps * d0 ? -4 : 0;
+  if (out) *out = st;
   return Status::ok();
 }
 
@@ -248,8 +336,8 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
   for (int i = 0; i < n; ++i) {
     if (!ps[i]->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
     if (ps[i]->dim != ps[0]->dim || ps[i]->k != ps[0]->k || ps[i]->stream != ps[0]->stream ||
-        ps[i]->post_same_order != ps[0]->post_same_order)
-      return Status{-1, "grouped V-cycle needs one dim, degree, stream and colour order"};
+        ps[i]->post_same_order != ps[0]->post_same_order || ps[i]->boundary_smoother != ps[0]->boundary_smoother)
+      return Status{-1, "grouped V-cycle needs one dim, degree, stream, colour order and smoother kernel"};
     Lmax = ps[i]->L > Lmax ? ps[i]->L : Lmax;
   }
   const int dim = ps[0]->dim, k = ps[0]->k, nc = 1 << dim;
@@ -264,7 +352,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
       if (ps[i]->L >= lvl) mem.push_back({ps[i]->geom(lvl), level_b(i, lvl), level_x(i, lvl)});
     for (int j = 0; j < nc; ++j) {
       const int c = reverse ? nc - 1 - j : j;
-      VPS_HIP(launch_colour_pass_group(dim, k, prec, false, c, mem.data(), (int)mem.size(), st));
+      VPS_HIP(launch_colour_pass_group(dim, k, prec, vcycle_mode(ps[0]), c, mem.data(), (int)mem.size(), st));
     }
     return Status::ok();
   };

@@ -43,6 +43,7 @@ struct Problem {
   std::vector<void*> allocs;
   size_t bytes = 0;
   bool post_same_order = false;
+  bool boundary_smoother = false;  // V-cycles smooth with the Boundary colour-pass kernel
 
   ~Problem();
   bool has(int prec) const;
@@ -63,6 +64,9 @@ Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const v
 Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x);
 Status coarse_solve(Problem* p, int prec, const void* b, void* x);
 Status vcycle(Problem* p, int prec, const void* b, void* x);
+// V-cycle with `top` as its finest level: b, x live on level `top`, levels below use the
+// hierarchy's buffers (top < L leaves levels above untouched).
+Status vcycle_top(Problem* p, int prec, int top, const void* b, void* x);
 // V-cycles of n problems of the same (dim, degree), all on one stream, in lockstep: every colour
 // pass of a level is one packed launch over the problems that have that level.  Each problem's
 // arithmetic (and result) is exactly that of vcycle() on it alone.
@@ -74,6 +78,10 @@ struct SolveStats {
   int status = 0;
 };
 Status pcg(Problem* p, int mode, const double* b, double* x, double rtol, int maxit, SolveStats* st);
+// Full multigrid: b_levels[l-1] is the right-hand side on level l (l = 1..L), all in `prec`;
+// x (level L, `prec`) receives the result.  st->iterations counts the V-cycles after the
+// nested iteration; synchronises once per V-cycle on the finest level.
+Status fmg(Problem* p, int prec, const void* const* b_levels, void* x, double eps, int maxit, SolveStats* st);
 
 // Stepwise CG (used by the server): same arithmetic as pcg(), one iteration per call.
 struct CgState {

@@ -9,6 +9,10 @@
 // applied by sum factorisation with the partial products reused across
 // directions (Sec. 3.1.1), and A_j^{-1} = (S x..x S)(sum Lambda)^{-1}(S x..x S)^T.
 // Additive mode skips the residual: x^I += A_j^{-1} b_j^I.
+// Boundary mode (Sec. 4.1.3, eq:A_ib_2d/3d) uses that the local solver is exact:
+//   x_j^I <- A_j^{-1} (b_j^I - A^{IB} x_j^B),
+// i.e. the residual is formed with the patch interior taken as zero and the
+// interior is overwritten, so x^I is never loaded.
 //
 // Mapping (designed for CDNA4, not a translation of the paper's CUDA):
 //  * a workgroup owns PPW patches that are consecutive along x0 inside the
@@ -110,12 +114,13 @@ __device__ __forceinline__ const DevTables<T>& tab_fresh(int k) {
 
 // One workgroup's share of a colour pass: patches of block `blk` of the colour described by
 // (p0, p1, p2, cnt0, cnt1, groups0) on a level with n1d nodes per direction.
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, int MODE>
 __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T* __restrict__ b, T* __restrict__ x,
                                                   long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
                                                   int groups0, T res_scale, T sol_scale, unsigned blk) {
   constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
   constexpr int PPW = SmootherShape<D, K>::PPW, NT = SmootherShape<D, K>::NT;
+  constexpr bool ADD = MODE == kModeAdditive, BND = MODE == kModeBoundary;
   using L = SmootherLds<D, K, T, ADD>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
@@ -167,13 +172,17 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
     const int st = D == 3 ? ld2 : ld1;
 #pragma unroll
     for (int i = 0; i < m; ++i) bpre[rr][i] = bo[off + i * st];
+    if constexpr (!BND) {
 #pragma unroll
-    for (int i = 0; i < m; ++i) xpre[rr][i] = xo[off + i * st];
+      for (int i = 0; i < m; ++i) xpre[rr][i] = xo[off + i * st];
+    }
   }
 
   // ---- closure segment -> LDS X [j2][j1][c].  Work item = (column c, row j1 in 3D); the
   // slowest axis is walked unrolled.  Every closure node lies inside the grid: loads are
   // unconditional and Dirichlet nodes are replaced by 0 (boundary entries of x are ignored).
+  // Boundary mode also replaces patch-interior nodes by 0 and does not load them: a column
+  // strictly inside a patch along x0 (and x1 in 3D) needs only its two end nodes.
   if constexpr (!ADD) {
     T* X = bufB;
     constexpr int NW = D == 3 ? RS * n : RS;
@@ -187,9 +196,17 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       if constexpr (D == 3) bad = bad || (j1 == 0 && lo1) || (j1 == n - 1 && hi1);
       const int base = (D == 3 ? j1 * ld1 : 0) + cl;
       const int sstride = D == 3 ? ld2 : ld1;
+      // column strictly inside a patch (Boundary mode: its nodes 1..n-2 are patch-interior)
+      const bool inner = BND && cl % (2 * K) != 0 && (D == 2 || (j1 > 0 && j1 < n - 1));
       T v[n];
 #pragma unroll
-      for (int j = 0; j < n; ++j) v[j] = xo[base + j * sstride];
+      for (int j = 0; j < n; ++j) {
+        if (BND && j > 0 && j < n - 1) {
+          v[j] = inner ? T(0) : xo[base + j * sstride];
+        } else {
+          v[j] = xo[base + j * sstride];
+        }
+      }
       const bool lo = D == 3 ? lo2 : lo1, hi = D == 3 ? hi2 : hi1;
       if (c < seg) {
 #pragma unroll
@@ -402,7 +419,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
-          xo[loff[rr] + i * ld2] = fma(sol_scale, s, xpre[rr][i]);
+          xo[loff[rr] + i * ld2] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
         }
       }
     }
@@ -528,32 +545,32 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           T s = T(0);
 #pragma unroll
           for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
-          xo[loff[rr] + i * ld1] = fma(sol_scale, s, xpre[rr][i]);
+          xo[loff[rr] + i * ld1] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
         }
       }
     }
   }
 }
 
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, int MODE>
 __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
     const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
     int groups0, T res_scale, T sol_scale) {
-  __shared__ T smem[SmootherLds<D, K, T, ADD>::total];
-  colour_pass_block<D, K, T, ADD>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
+  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive>::total];
+  colour_pass_block<D, K, T, MODE>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
                                   xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Several colour passes of the same (dim, degree, precision, colour) on different vectors and
 // levels in one launch: entry e owns blocks [begin[e], begin[e+1]).
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, int MODE>
 __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_group_kernel(ColourPassGroup grp) {
-  __shared__ T smem[SmootherLds<D, K, T, ADD>::total];
+  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive>::total];
   const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
   int e = 0;
   while (e + 1 < grp.n && (unsigned)grp.e[e + 1].block_begin <= g) ++e;
   const ColourPassDesc& d = grp.e[e];
-  colour_pass_block<D, K, T, ADD>(smem, (const T*)d.b, (T*)d.x, d.n1d, d.p[0], d.p[1], d.p[2], d.cnt0, d.cnt1,
+  colour_pass_block<D, K, T, MODE>(smem, (const T*)d.b, (T*)d.x, d.n1d, d.p[0], d.p[1], d.p[2], d.cnt0, d.cnt1,
                                   d.groups0, (T)d.res_scale, (T)d.sol_scale, g - (unsigned)d.block_begin);
 }
 
@@ -583,7 +600,7 @@ struct ColourGrid {
   }
 };
 
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, int MODE>
 static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
   constexpr int NT = SmootherShape<D, K>::NT;
   const ColourGrid<D, K> cg(g, colour);
@@ -592,12 +609,12 @@ static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void
   // Abar_h = h^(d-2) Abar_1 ; A_j,h^{-1} = h^(2-d) A_j,1^{-1}
   const T res_scale = (T)(D == 3 ? g.h : 1.0);
   const T sol_scale = (T)(D == 3 ? 1.0 / g.h : 1.0);
-  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, ADD>), dim3((unsigned)cg.blocks), dim3(NT), 0, st, (const T*)b,
+  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, MODE>), dim3((unsigned)cg.blocks), dim3(NT), 0, st, (const T*)b,
                      (T*)x, g.n1d, cg.p[0], cg.p[1], cg.p[2], cg.cnt[0], cg.cnt[1], cg.groups0, res_scale, sol_scale);
   return hipGetLastError();
 }
 
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, int MODE>
 static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, hipStream_t st) {
   constexpr int NT = SmootherShape<D, K>::NT;
   ColourPassGroup grp;
@@ -605,7 +622,7 @@ static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, 
   long long total = 0;
   auto flush = [&]() -> hipError_t {
     if (grp.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((colour_pass_group_kernel<D, K, T, ADD>), dim3((unsigned)total), dim3(NT), 0, st, grp);
+    hipLaunchKernelGGL((colour_pass_group_kernel<D, K, T, MODE>), dim3((unsigned)total), dim3(NT), 0, st, grp);
     grp.n = 0;
     total = 0;
     return hipGetLastError();
@@ -636,60 +653,73 @@ static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, 
   return flush();
 }
 
+template <int D, int K, typename T>
+static hipError_t dispatch_mode(const LevelGeom& g, int mode, int colour, const void* b, void* x, hipStream_t st) {
+  switch (mode) {
+    case kModeMultiplicative: return launch_one<D, K, T, kModeMultiplicative>(g, colour, b, x, st);
+    case kModeAdditive: return launch_one<D, K, T, kModeAdditive>(g, colour, b, x, st);
+    case kModeBoundary: return launch_one<D, K, T, kModeBoundary>(g, colour, b, x, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int D, int K>
-static hipError_t dispatch_prec(const LevelGeom& g, int prec, bool add, int colour, const void* b, void* x,
+static hipError_t dispatch_prec(const LevelGeom& g, int prec, int mode, int colour, const void* b, void* x,
                                 hipStream_t st) {
-  if (prec == 0)
-    return add ? launch_one<D, K, double, true>(g, colour, b, x, st) : launch_one<D, K, double, false>(g, colour, b, x, st);
-  return add ? launch_one<D, K, float, true>(g, colour, b, x, st) : launch_one<D, K, float, false>(g, colour, b, x, st);
+  return prec == 0 ? dispatch_mode<D, K, double>(g, mode, colour, b, x, st)
+                   : dispatch_mode<D, K, float>(g, mode, colour, b, x, st);
 }
 
 template <int D>
-static hipError_t dispatch_k(const LevelGeom& g, int prec, bool add, int colour, const void* b, void* x,
+static hipError_t dispatch_k(const LevelGeom& g, int prec, int mode, int colour, const void* b, void* x,
                              hipStream_t st) {
   switch (g.k) {
-    case 1: return dispatch_prec<D, 1>(g, prec, add, colour, b, x, st);
-    case 2: return dispatch_prec<D, 2>(g, prec, add, colour, b, x, st);
-    case 3: return dispatch_prec<D, 3>(g, prec, add, colour, b, x, st);
-    case 4: return dispatch_prec<D, 4>(g, prec, add, colour, b, x, st);
-    case 5: return dispatch_prec<D, 5>(g, prec, add, colour, b, x, st);
-    case 6: return dispatch_prec<D, 6>(g, prec, add, colour, b, x, st);
-    case 7: return dispatch_prec<D, 7>(g, prec, add, colour, b, x, st);
+    case 1: return dispatch_prec<D, 1>(g, prec, mode, colour, b, x, st);
+    case 2: return dispatch_prec<D, 2>(g, prec, mode, colour, b, x, st);
+    case 3: return dispatch_prec<D, 3>(g, prec, mode, colour, b, x, st);
+    case 4: return dispatch_prec<D, 4>(g, prec, mode, colour, b, x, st);
+    case 5: return dispatch_prec<D, 5>(g, prec, mode, colour, b, x, st);
+    case 6: return dispatch_prec<D, 6>(g, prec, mode, colour, b, x, st);
+    case 7: return dispatch_prec<D, 7>(g, prec, mode, colour, b, x, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_colour_pass(const LevelGeom& g, int prec, bool additive, int colour, const void* b, void* x,
+hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour, const void* b, void* x,
                               hipStream_t st) {
-  return g.dim == 2 ? dispatch_k<2>(g, prec, additive, colour, b, x, st)
-                    : dispatch_k<3>(g, prec, additive, colour, b, x, st);
+  return g.dim == 2 ? dispatch_k<2>(g, prec, mode, colour, b, x, st) : dispatch_k<3>(g, prec, mode, colour, b, x, st);
 }
 
+// Packed launches exist for the two multiplicative kernels (the V-cycle smoothers).
 template <int D, int K>
-static hipError_t group_prec(int prec, bool add, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
-  if (prec == 0)
-    return add ? launch_group<D, K, double, true>(colour, m, nm, st) : launch_group<D, K, double, false>(colour, m, nm, st);
-  return add ? launch_group<D, K, float, true>(colour, m, nm, st) : launch_group<D, K, float, false>(colour, m, nm, st);
+static hipError_t group_prec(int prec, int mode, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
+  if (mode == kModeMultiplicative)
+    return prec == 0 ? launch_group<D, K, double, kModeMultiplicative>(colour, m, nm, st)
+                     : launch_group<D, K, float, kModeMultiplicative>(colour, m, nm, st);
+  if (mode == kModeBoundary)
+    return prec == 0 ? launch_group<D, K, double, kModeBoundary>(colour, m, nm, st)
+                     : launch_group<D, K, float, kModeBoundary>(colour, m, nm, st);
+  return hipErrorInvalidValue;
 }
 
 template <int D>
-static hipError_t group_k(int k, int prec, bool add, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
+static hipError_t group_k(int k, int prec, int mode, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
   switch (k) {
-    case 1: return group_prec<D, 1>(prec, add, colour, m, nm, st);
-    case 2: return group_prec<D, 2>(prec, add, colour, m, nm, st);
-    case 3: return group_prec<D, 3>(prec, add, colour, m, nm, st);
-    case 4: return group_prec<D, 4>(prec, add, colour, m, nm, st);
-    case 5: return group_prec<D, 5>(prec, add, colour, m, nm, st);
-    case 6: return group_prec<D, 6>(prec, add, colour, m, nm, st);
-    case 7: return group_prec<D, 7>(prec, add, colour, m, nm, st);
+    case 1: return group_prec<D, 1>(prec, mode, colour, m, nm, st);
+    case 2: return group_prec<D, 2>(prec, mode, colour, m, nm, st);
+    case 3: return group_prec<D, 3>(prec, mode, colour, m, nm, st);
+    case 4: return group_prec<D, 4>(prec, mode, colour, m, nm, st);
+    case 5: return group_prec<D, 5>(prec, mode, colour, m, nm, st);
+    case 6: return group_prec<D, 6>(prec, mode, colour, m, nm, st);
+    case 7: return group_prec<D, 7>(prec, mode, colour, m, nm, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_colour_pass_group(int dim, int k, int prec, bool additive, int colour,
-                                    const ColourPassMember* members, int n_members, hipStream_t st) {
-  return dim == 2 ? group_k<2>(k, prec, additive, colour, members, n_members, st)
-                  : group_k<3>(k, prec, additive, colour, members, n_members, st);
+hipError_t launch_colour_pass_group(int dim, int k, int prec, int mode, int colour, const ColourPassMember* members,
+                                    int n_members, hipStream_t st) {
+  return dim == 2 ? group_k<2>(k, prec, mode, colour, members, n_members, st)
+                  : group_k<3>(k, prec, mode, colour, members, n_members, st);
 }
 
 hipError_t init_smoother_tables() {

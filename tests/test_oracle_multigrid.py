@@ -45,21 +45,7 @@ def test_pcg_iterations_flat_in_h(d, k, levels):
     assert max(its) <= 12
 
 
-def _f1_rhs(d, k, level):
-    """b for f = 1: Kronecker product of the 1D load vector of 1 (row sums of h*Mhat)."""
-    _, Mhat = basis.reference_matrices(k)
-    h = mesh.mesh_size(level)
-    g = np.zeros(mesh.n1d(k, level))
-    for c in range(2 ** level):
-        g[k * c:k * c + k + 1] += h * Mhat.sum(1)
-    B = np.ones((1,) * d)
-    for a in range(d):
-        shape = [1] * d
-        shape[d - 1 - a] = len(g)
-        B = B * g.reshape(shape)
-    b = B.reshape(-1)
-    b[mesh.boundary_mask(d, k, level)] = 0
-    return b
+_f1_rhs = rhs.rhs_constant
 
 
 def test_f1_rhs_against_pointwise_quadrature():

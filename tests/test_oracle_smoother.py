@@ -174,3 +174,29 @@ def test_local_patch_update_matches_colour_pass():
         got = smoother.patch_update_local(d, k, level, x[mesh.patch_closure_ids(d, k, level, v)],
                                           b[mesh.patch_interior_ids(d, k, level, v)])
         assert np.allclose(got, y[mesh.patch_interior_ids(d, k, level, v)], atol=1e-12)
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 2), (2, 5), (3, 1), (3, 2), (3, 3)])
+def test_a_ib_kronecker_blocks_equal_the_assembled_patch_matrix(d, k):
+    """eq:A_ib_2d/3d: the Kronecker blocks reproduce the interior-row, boundary-column block of the
+    closure matrix assembled from cell matrices, and their columns are exactly the boundary nodes."""
+    h = 0.125
+    A_ib, cols = smoother.a_ib_kronecker(d, k, h)
+    Ac = smoother.patch_closure_matrix(d, k, h)
+    I = smoother.patch_interior_local(d, k)
+    B = np.setdiff1d(np.arange((2 * k + 1) ** d), I)
+    assert np.array_equal(np.sort(cols), B)
+    assert np.allclose(A_ib, Ac[np.ix_(I, cols)], atol=1e-13 * np.abs(Ac).max())
+
+
+@pytest.mark.parametrize("d,k,level", [(2, 1, 3), (2, 3, 3), (3, 1, 3), (3, 2, 2), (3, 3, 2)])
+def test_boundary_colour_pass_equals_the_fused_one(d, k, level):
+    rng = np.random.default_rng(7)
+    N = mesh.n1d(k, level) ** d
+    bm = mesh.boundary_mask(d, k, level)
+    b, x = rng.standard_normal(N), rng.standard_normal(N)
+    b[bm] = x[bm] = 0
+    for c in range(2 ** d):
+        ref = smoother.colour_pass(d, k, level, b, x, c)
+        got = smoother.colour_pass_boundary(d, k, level, b, x, c)
+        assert np.allclose(got, ref, atol=1e-12 * np.abs(ref).max()), c
