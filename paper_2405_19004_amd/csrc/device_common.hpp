@@ -24,6 +24,8 @@ struct DevTables {
   T Rb[kMaxDegree * (4 * kMaxDegree + 1)];  // restriction band rows k x (4k+1)
   T inv3[kMaxM * kMaxM * kMaxM];  // 1 / (lam[a2] + lam[a1] + lam[a0]), index (a2*m + a1)*m + a0
   T inv2[kMaxM * kMaxM];          // 1 / (lam[a1] + lam[a0]),           index a1*m + a0
+  T Ah[(kMaxDegree + 1) * (kMaxDegree + 1)];  // reference cell stiffness (k+1) x (k+1)
+  T Mh[(kMaxDegree + 1) * (kMaxDegree + 1)];  // reference cell mass
 };
 
 template <typename T>
@@ -36,6 +38,7 @@ inline void fill_dev_tables(int k, DevTables<T>& out) {
   for (int i = 0; i < k * n; ++i) { out.Mb[i] = (T)t.Mband[i]; out.Ab[i] = (T)t.Aband[i]; }
   for (int i = 0; i < n * np; ++i) out.P[i] = (T)t.P[i];
   for (int i = 0; i < k * (4 * k + 1); ++i) out.Rb[i] = (T)t.Rband[i];
+  for (int i = 0; i < np * np; ++i) { out.Ah[i] = (T)t.Ahat[i]; out.Mh[i] = (T)t.Mhat[i]; }
   for (int a2 = 0; a2 < m; ++a2)
     for (int a1 = 0; a1 < m; ++a1) {
       out.inv2[a2 * m + a1] = (T)(1.0 / (t.lam[a2] + t.lam[a1]));

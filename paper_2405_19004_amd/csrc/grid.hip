@@ -220,6 +220,161 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   }
 }
 
+// ------------------------------------------------- operator, 3D streaming form
+//
+// y = A2 (M1 M0 x) + M2 (A1 M0 x + M1 A0 x) with the assembled 1D matrices applied in cell
+// form: along each axis a cell c contributes Ahat/Mhat (reference cell, compile-time indices,
+// SGPR operands) to its K+1 nodes, a vertex sums the contributions of its two cells.  A
+// workgroup owns a TX x TY column tile of the (x0, x1) plane and walks a chunk of cells along
+// x2: every node plane is loaded once into LDS (with a K-node halo in x0 and x1 only), reduced
+// in-plane (x0 then x1), and the x2 contraction runs in registers over the K+1 planes of the
+// current cell, carrying the left-cell part of the next vertex.  The z halo is one cell per
+// chunk instead of per tile, which removes most of the recomputation of a cubic tile.
+
+template <int K>
+struct OpStream {
+  static constexpr int CX = K == 1 ? 16 : K == 2 ? 8 : K == 3 ? 5 : K == 4 ? 4 : K == 5 ? 3 : 2;
+  static constexpr int TX = K * CX, TY = K * CX;        // outputs per plane tile
+  static constexpr int NT = TX * TY;                    // one thread per output column
+  static constexpr int IX = TX + K + 1, IY = TY + K + 1;  // input extents [o - K, o + T]
+};
+
+template <int K, typename T, bool RESID>
+__global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* __restrict__ x, const T* __restrict__ b,
+                                                                     T* __restrict__ y, long long n1d, int tiles0,
+                                                                     int tiles1, int cz, T scale) {
+  using S = OpStream<K>;
+  constexpr int NT = S::NT, TX = S::TX, TY = S::TY, IX = S::IX, IY = S::IY, CX = S::CX, NP = K + 1;
+  __shared__ T X[IY * IX];       // node plane with halo, [r][c]
+  __shared__ T Rm[IY * TX];      // M0 x, [r][c]
+  __shared__ T Ra[IY * TX];      // A0 x
+  __shared__ T Pm[TY * TX];      // M1 M0 x
+  __shared__ T Pq[TY * TX];      // A1 M0 x + M1 A0 x
+
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles0;
+  const int ty = (blk / tiles0) % tiles1;
+  const int chunk = blk / (tiles0 * tiles1);
+  const long long o0 = (long long)tx * TX, o1 = (long long)ty * TY;
+  const long long ncz = (n1d - 1) / K;  // cells along x2
+  const long long g0 = (long long)chunk * cz;
+  const long long g1 = g0 + cz < ncz ? g0 + cz : ncz;
+  const long long n1d2 = n1d * n1d;
+  const int tid = threadIdx.x;
+  const int px = tid % TX, py = tid / TX;
+  const long long gx = o0 + px, gy = o1 + py;
+  const bool col_out = !is_bnd(gx, n1d) && !is_bnd(gy, n1d) && gx < n1d && gy < n1d;
+
+  // (M1 M0 x, A1 M0 x + M1 A0 x) of node plane zg at this thread's column
+  auto plane = [&](long long zg, T& pm, T& pq) {
+    const bool zin = zg >= 1 && zg <= n1d - 2;
+    const T* xz = x + (zin ? zg : 0) * n1d2;
+    for (int i = tid; i < IY * IX; i += NT) {
+      const int r = i / IX, c = i - r * IX;
+      const long long sy = o1 - K + r, sx = o0 - K + c;
+      const bool ok = zin && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
+      X[i] = ok ? xz[sy * n1d + sx] : T(0);
+    }
+    __syncthreads();
+    // x0: task (row r, cell cx): outputs cx*K + li from the 2K+1 inputs of cells cx-1 and cx
+    for (int task = tid; task < IY * CX; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+      const int r = task / CX, cx = task - r * CX;
+      T in[2 * K + 1];
+#pragma unroll
+      for (int t = 0; t <= 2 * K; ++t) in[t] = X[r * IX + cx * K + t];
+#pragma unroll
+      for (int li = 0; li < K; ++li) {
+        T sm = T(0), sa = T(0);
+        if (li == 0) {
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            sm = fma(tb.Mh[K * NP + j], in[j], sm);
+            sa = fma(tb.Ah[K * NP + j], in[j], sa);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          sm = fma(tb.Mh[li * NP + j], in[K + j], sm);
+          sa = fma(tb.Ah[li * NP + j], in[K + j], sa);
+        }
+        Rm[r * TX + cx * K + li] = sm;
+        Ra[r * TX + cx * K + li] = sa;
+      }
+    }
+    __syncthreads();
+    // x1: task (column c, cell cy)
+    for (int task = tid; task < TX * CX; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+      const int cy = task / TX, c = task - cy * TX;
+      T im[2 * K + 1], ia[2 * K + 1];
+#pragma unroll
+      for (int t = 0; t <= 2 * K; ++t) {
+        im[t] = Rm[(cy * K + t) * TX + c];
+        ia[t] = Ra[(cy * K + t) * TX + c];
+      }
+#pragma unroll
+      for (int li = 0; li < K; ++li) {
+        T su = T(0), sv = T(0);
+        if (li == 0) {
+#pragma unroll
+          for (int j = 0; j < NP; ++j) {
+            su = fma(tb.Mh[K * NP + j], im[j], su);
+            sv = fma(tb.Ah[K * NP + j], im[j], sv);
+            sv = fma(tb.Mh[K * NP + j], ia[j], sv);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          su = fma(tb.Mh[li * NP + j], im[K + j], su);
+          sv = fma(tb.Ah[li * NP + j], im[K + j], sv);
+          sv = fma(tb.Mh[li * NP + j], ia[K + j], sv);
+        }
+        Pm[(cy * K + li) * TX + c] = su;
+        Pq[(cy * K + li) * TX + c] = sv;
+      }
+    }
+    __syncthreads();
+    pm = Pm[tid];
+    pq = Pq[tid];
+  };
+
+  // x2 in cell form over planes g*K .. g*K+K
+  T zm[NP], zq[NP];
+  T carry = T(0);
+  zm[0] = zq[0] = T(0);
+  if (g0 > 0) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) plane((g0 - 1) * K + j, zm[j], zq[j]);
+    const DevTables<T>& tb = gtab_fresh<T>(K);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
+    zm[0] = zm[K];
+    zq[0] = zq[K];
+  }
+  for (long long g = g0; g < g1; ++g) {
+#pragma unroll
+    for (int j = 1; j < NP; ++j) plane(g * K + j, zm[j], zq[j]);
+    const DevTables<T>& tb = gtab_fresh<T>(K);
+#pragma unroll
+    for (int li = 0; li < K; ++li) {
+      T s = li == 0 ? carry : T(0);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) s = fma(tb.Ah[li * NP + j], zm[j], fma(tb.Mh[li * NP + j], zq[j], s));
+      const long long zg = g * K + li;
+      if (col_out && zg >= 1) {
+        const long long gi = zg * n1d2 + gy * n1d + gx;
+        y[gi] = RESID ? b[gi] - scale * s : scale * s;
+      }
+    }
+    carry = T(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
+    zm[0] = zm[K];
+    zq[0] = zq[K];
+  }
+}
+
 // ----------------------------------------------------------- prolongation
 
 // Coarse cells per tile.
@@ -537,6 +692,130 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
+// ----------------------------------------------- restriction, 3D streaming form
+//
+// rc = (P1 x P1 x P1)^T rf in cell form: along each axis the fine nodes are split into
+// half-open runs 2KC .. 2KC + 2K - 1, one per coarse cell C, and each run maps to the K+1
+// coarse nodes of its cell with P[q][a] = phi_a(fine position q); a coarse vertex sums the
+// parts of its two cells (the fine node on the vertex lies in one run only, so every entry of
+// P1 is used once).  A workgroup owns a TX x TX tile of coarse columns and walks a
+// chunk of coarse cells along x2, reducing every fine plane in-plane (x0, then x1) and
+// accumulating the x2 part in registers, so the fine vector is read once and nothing is
+// staged in global memory.  Fine boundary nodes count as 0; coarse boundary nodes are
+// written 0.
+
+template <int K>
+struct ResStream {
+  static constexpr int CX = K == 1 ? 8 : K == 2 ? 4 : K == 3 ? 3 : K <= 5 ? 2 : 1;
+  static constexpr int TX = K * CX;                // coarse outputs per tile row
+  static constexpr int NT = TX * TX;               // one thread per coarse column
+  static constexpr int IX = 2 * TX + 2 * K;        // fine extent [2o - 2K, 2o + 2TX - 1]
+};
+
+template <int K, typename T>
+__global__ __launch_bounds__((ResStream<K>::NT)) void restrict_stream_kernel(const T* __restrict__ rf,
+                                                                            T* __restrict__ rc, long long nf,
+                                                                            long long nc, int tiles, int czc) {
+  using S = ResStream<K>;
+  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, NP = K + 1, RUN = 2 * K;
+  __shared__ T X[IX * IX];   // fine plane with halo, [r][c]
+  __shared__ T Rx[IX * TX];  // reduced along x0, [fine row][coarse col]
+  __shared__ T Pl[TX * TX];  // reduced along x0 and x1
+
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles;
+  const int ty = (blk / tiles) % tiles;
+  const int chunk = blk / (tiles * tiles);
+  const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;  // first coarse node of the tile
+  const long long ncz = (nc - 1) / K;                                // coarse cells along x2
+  const long long c0 = (long long)chunk * czc;
+  const long long c1 = c0 + czc < ncz ? c0 + czc : ncz;
+  const long long nf2 = nf * nf, nc2 = nc * nc;
+  const int tid = threadIdx.x;
+  const int px = tid % TX, py = tid / TX;
+  const long long gx = o0 + px, gy = o1 + py;
+  const bool col_valid = gx < nc && gy < nc;
+  const bool col_bnd = gx == 0 || gy == 0 || gx == nc - 1 || gy == nc - 1;
+
+  // in[t] = fine nodes 2K(C-1) + t, t < 4K: the runs of cells C-1 and C; output a of cell C
+  auto reduce = [](const DevTables<T>& tb, const T* in, int a) -> T {
+    T s = T(0);
+    if (a == 0) {
+#pragma unroll
+      for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + K], in[q], s);
+    }
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + a], in[RUN + q], s);
+    return s;
+  };
+
+  auto plane = [&](long long zf) -> T {
+    const bool zin = zf >= 1 && zf <= nf - 2;
+    const T* fz = rf + (zin ? zf : 0) * nf2;
+    for (int i = tid; i < IX * IX; i += NT) {
+      const int r = i / IX, c = i - r * IX;
+      const long long fy = 2 * o1 - 2 * K + r, fx = 2 * o0 - 2 * K + c;
+      const bool ok = zin && fy >= 1 && fy <= nf - 2 && fx >= 1 && fx <= nf - 2;
+      X[i] = ok ? fz[fy * nf + fx] : T(0);
+    }
+    __syncthreads();
+    for (int task = tid; task < IX * CX; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+      const int r = task / CX, cx = task - r * CX;
+      T in[2 * RUN];
+#pragma unroll
+      for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * IX + RUN * cx + t];
+#pragma unroll
+      for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = reduce(tb, in, a);
+    }
+    __syncthreads();
+    for (int task = tid; task < TX * CX; task += NT) {
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+      const int cy = task / TX, c = task - cy * TX;
+      T in[2 * RUN];
+#pragma unroll
+      for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(RUN * cy + t) * TX + c];
+#pragma unroll
+      for (int a = 0; a < K; ++a) Pl[(cy * K + a) * TX + c] = reduce(tb, in, a);
+    }
+    __syncthreads();
+    return Pl[tid];
+  };
+
+  // x2: coarse cell C owns fine planes 2KC .. 2KC + 2K - 1; its right-vertex part carries over
+  T carry = T(0);
+  if (c0 > 0) {
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+      const T v = plane(RUN * (c0 - 1) + q);
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+      carry = fma(tb.P[q * NP + K], v, carry);
+    }
+  }
+  for (long long C = c0; C < c1; ++C) {
+    T acc[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+      const T v = plane(RUN * C + q);
+      const DevTables<T>& tb = gtab_fresh<T>(K);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) acc[a] = fma(tb.P[q * NP + a], v, acc[a]);
+    }
+    if (col_valid) {
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        const long long zc = K * C + a;
+        const T val = a == 0 ? acc[0] + carry : acc[a];
+        rc[zc * nc2 + gy * nc + gx] = (col_bnd || zc == 0) ? T(0) : val;
+      }
+    }
+    carry = acc[K];
+  }
+  if (c1 == ncz && col_valid) rc[(nc - 1) * nc2 + gy * nc + gx] = T(0);
+}
+
 // ------------------------------------------------------- boundary and rhs
 
 // Zero every boundary node: thread per node of the d-1 dimensional faces.
@@ -653,8 +932,31 @@ namespace {
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+template <int K, typename T>
+hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+  using S = OpStream<K>;
+  const int t0 = ceil_div(g.ncells, S::CX), t1 = t0;
+  // enough workgroups to fill the chip, chunks of at least 4 cells along x2
+  const long long tiles = (long long)t0 * t1;
+  long long chunks = (2048 + tiles - 1) / tiles;
+  if (chunks > g.ncells / 4) chunks = g.ncells / 4;
+  if (chunks < 1) chunks = 1;
+  const int cz = (int)((g.ncells + chunks - 1) / chunks);
+  chunks = (g.ncells + cz - 1) / cz;
+  const long long blocks = tiles * chunks;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const T scale = (T)g.h;  // A_h = h A_1 in 3D
+  if (b)
+    hipLaunchKernelGGL((op_stream_kernel<K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
+                       (const T*)b, (T*)y, g.n1d, t0, t1, cz, scale);
+  else
+    hipLaunchKernelGGL((op_stream_kernel<K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
+                       (const T*)nullptr, (T*)y, g.n1d, t0, t1, cz, scale);
+  return hipGetLastError();
+}
+
 template <int D, int K, typename T>
-hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
   using S = OpShape<D, K>;
   const int t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1), t2 = D == 3 ? ceil_div(g.ncells, S::C2) : 1;
   const long long blocks = (long long)t0 * t1 * t2;
@@ -666,6 +968,21 @@ hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, 
     hipLaunchKernelGGL((op_tile_kernel<D, K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
                        (const T*)nullptr, (T*)y, g.n1d, t0, t1, scale);
   return hipGetLastError();
+}
+
+#ifdef VPS_OP_TILE_3D
+constexpr bool kOpStream3D = false;  // cubic-tile operator in 3D as well (comparison builds)
+#else
+constexpr bool kOpStream3D = true;
+#endif
+
+template <int D, int K, typename T>
+hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+  if constexpr (D == 3 && kOpStream3D) {
+    return op_stream_launch<K, T>(g, x, b, y, st);
+  } else {
+    return op_tile_launch<D, K, T>(g, x, b, y, st);
+  }
 }
 
 template <int D, int K, typename T>
@@ -680,6 +997,12 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
   return hipGetLastError();
 }
 
+#ifdef VPS_RES_PASSES_3D
+constexpr bool kResStream3D = false;  // separable passes in 3D as well (comparison builds)
+#else
+constexpr bool kResStream3D = true;
+#endif
+
 template <int D, int K, typename T>
 hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t1, void* t2) {
   const int nf = (int)fine.n1d, nc = (int)(K * (fine.ncells / 2) + 1);
@@ -690,7 +1013,20 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
   };
   if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
     return hipErrorInvalidConfiguration;
-  if (D == 2) {
+  if (D == 3 && kResStream3D) {
+    using S = ResStream<K>;
+    const int tiles = ceil_div(nc, S::TX);
+    const long long ncz = (nc - 1) / K;
+    long long chunks = (2048 + (long long)tiles * tiles - 1) / ((long long)tiles * tiles);
+    if (chunks > ncz / 2) chunks = ncz / 2;
+    if (chunks < 1) chunks = 1;
+    const int czc = (int)((ncz + chunks - 1) / chunks);
+    chunks = (ncz + czc - 1) / czc;
+    const long long blocks = (long long)tiles * tiles * chunks;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((restrict_stream_kernel<K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)rf,
+                       (T*)rc, (long long)nf, (long long)nc, tiles, czc);
+  } else if (D == 2) {
     // x0: [nf][nf] -> T1 [nf][nc]; x1: T1 -> rc [nc][nc]
     hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, 1), dim3(256), 0, st, (const T*)rf,
                        (T*)t1, nf, nc, nf, 1);

