@@ -245,11 +245,16 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
                                                                      int tiles1, int cz, T scale) {
   using S = OpStream<K>;
   constexpr int NT = S::NT, TX = S::TX, TY = S::TY, IX = S::IX, IY = S::IY, CX = S::CX, NP = K + 1;
-  __shared__ T X[IY * IX];       // node plane with halo, [r][c]
-  __shared__ T Rm[IY * TX];      // M0 x, [r][c]
-  __shared__ T Ra[IY * TX];      // A0 x
-  __shared__ T Pm[TY * TX];      // M1 M0 x
-  __shared__ T Pq[TY * TX];      // A1 M0 x + M1 A0 x
+  constexpr int PL = IY * IX;                  // values of one input plane tile
+  constexpr int RB = (K * PL + NT - 1) / NT;   // prefetch registers per thread (one cell of planes)
+  constexpr int XS = K * PL > 2 * K * TY * TX ? K * PL : 2 * K * TY * TX;
+  // X (input planes) and, once X is consumed, Pm / Pq (in-plane results) share one buffer
+  __shared__ T XP[XS];
+  __shared__ T Rm[K * IY * TX];  // M0 x, [plane][r][c]
+  __shared__ T Ra[K * IY * TX];  // A0 x
+  T* X = XP;
+  T* Pm = XP;                    // M1 M0 x, [plane][r][c]
+  T* Pq = XP + K * TY * TX;      // A1 M0 x + M1 A0 x
 
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = blk % tiles0;
@@ -265,96 +270,129 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
   const long long gx = o0 + px, gy = o1 + py;
   const bool col_out = !is_bnd(gx, n1d) && !is_bnd(gy, n1d) && gx < n1d && gy < n1d;
 
-  // (M1 M0 x, A1 M0 x + M1 A0 x) of node plane zg at this thread's column
-  auto plane = [&](long long zg, T& pm, T& pq) {
-    const bool zin = zg >= 1 && zg <= n1d - 2;
-    const T* xz = x + (zin ? zg : 0) * n1d2;
-    for (int i = tid; i < IY * IX; i += NT) {
-      const int r = i / IX, c = i - r * IX;
-      const long long sy = o1 - K + r, sx = o0 - K + c;
-      const bool ok = zin && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
-      X[i] = ok ? xz[sy * n1d + sx] : T(0);
+  // registers <- nb node planes zs .. zs+nb-1 of the tile (Dirichlet and outside nodes 0)
+  T pre[RB];
+  auto fetch = [&](long long zs, int nb) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int i = rr * NT + tid;
+      const int j = i / PL, rem = i - j * PL;
+      const int r = rem / IX, c = rem - r * IX;
+      const long long zg = zs + j, sy = o1 - K + r, sx = o0 - K + c;
+      const bool ok = j < nb && zg >= 1 && zg <= n1d - 2 && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
+      pre[rr] = ok ? x[zg * n1d2 + sy * n1d + sx] : T(0);
     }
+  };
+  auto stage = [&](int nb) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int i = rr * NT + tid;
+      if (i < nb * PL) X[i] = pre[rr];
+    }
+  };
+  // X (nb planes) -> Pm, Pq (nb planes); ends after a barrier, results readable by every thread
+  auto reduce = [&](int nb) {
     __syncthreads();
-    // x0: task (row r, cell cx): outputs cx*K + li from the 2K+1 inputs of cells cx-1 and cx
-    for (int task = tid; task < IY * CX; task += NT) {
+    for (int task = tid; task < nb * IY * CX; task += NT) {
       const DevTables<T>& tb = gtab_fresh<T>(K);
-      const int r = task / CX, cx = task - r * CX;
+      const int j = task / (IY * CX), rem = task - j * (IY * CX);
+      const int r = rem / CX, cx = rem - r * CX;
       T in[2 * K + 1];
 #pragma unroll
-      for (int t = 0; t <= 2 * K; ++t) in[t] = X[r * IX + cx * K + t];
+      for (int t = 0; t <= 2 * K; ++t) in[t] = X[j * PL + r * IX + cx * K + t];
 #pragma unroll
       for (int li = 0; li < K; ++li) {
         T sm = T(0), sa = T(0);
         if (li == 0) {
 #pragma unroll
-          for (int j = 0; j < NP; ++j) {
-            sm = fma(tb.Mh[K * NP + j], in[j], sm);
-            sa = fma(tb.Ah[K * NP + j], in[j], sa);
+          for (int q = 0; q < NP; ++q) {
+            sm = fma(tb.Mh[K * NP + q], in[q], sm);
+            sa = fma(tb.Ah[K * NP + q], in[q], sa);
           }
         }
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          sm = fma(tb.Mh[li * NP + j], in[K + j], sm);
-          sa = fma(tb.Ah[li * NP + j], in[K + j], sa);
+        for (int q = 0; q < NP; ++q) {
+          sm = fma(tb.Mh[li * NP + q], in[K + q], sm);
+          sa = fma(tb.Ah[li * NP + q], in[K + q], sa);
         }
-        Rm[r * TX + cx * K + li] = sm;
-        Ra[r * TX + cx * K + li] = sa;
+        Rm[(j * IY + r) * TX + cx * K + li] = sm;
+        Ra[(j * IY + r) * TX + cx * K + li] = sa;
       }
     }
     __syncthreads();
-    // x1: task (column c, cell cy)
-    for (int task = tid; task < TX * CX; task += NT) {
+    for (int task = tid; task < nb * TX * CX; task += NT) {
       const DevTables<T>& tb = gtab_fresh<T>(K);
-      const int cy = task / TX, c = task - cy * TX;
+      const int j = task / (TX * CX), rem = task - j * (TX * CX);
+      const int cy = rem / TX, c = rem - cy * TX;
       T im[2 * K + 1], ia[2 * K + 1];
 #pragma unroll
       for (int t = 0; t <= 2 * K; ++t) {
-        im[t] = Rm[(cy * K + t) * TX + c];
-        ia[t] = Ra[(cy * K + t) * TX + c];
+        im[t] = Rm[(j * IY + cy * K + t) * TX + c];
+        ia[t] = Ra[(j * IY + cy * K + t) * TX + c];
       }
 #pragma unroll
       for (int li = 0; li < K; ++li) {
         T su = T(0), sv = T(0);
         if (li == 0) {
 #pragma unroll
-          for (int j = 0; j < NP; ++j) {
-            su = fma(tb.Mh[K * NP + j], im[j], su);
-            sv = fma(tb.Ah[K * NP + j], im[j], sv);
-            sv = fma(tb.Mh[K * NP + j], ia[j], sv);
+          for (int q = 0; q < NP; ++q) {
+            su = fma(tb.Mh[K * NP + q], im[q], su);
+            sv = fma(tb.Ah[K * NP + q], im[q], sv);
+            sv = fma(tb.Mh[K * NP + q], ia[q], sv);
           }
         }
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          su = fma(tb.Mh[li * NP + j], im[K + j], su);
-          sv = fma(tb.Ah[li * NP + j], im[K + j], sv);
-          sv = fma(tb.Mh[li * NP + j], ia[K + j], sv);
+        for (int q = 0; q < NP; ++q) {
+          su = fma(tb.Mh[li * NP + q], im[K + q], su);
+          sv = fma(tb.Ah[li * NP + q], im[K + q], sv);
+          sv = fma(tb.Mh[li * NP + q], ia[K + q], sv);
         }
-        Pm[(cy * K + li) * TX + c] = su;
-        Pq[(cy * K + li) * TX + c] = sv;
+        Pm[(j * TY + cy * K + li) * TX + c] = su;
+        Pq[(j * TY + cy * K + li) * TX + c] = sv;
       }
     }
     __syncthreads();
-    pm = Pm[tid];
-    pq = Pq[tid];
   };
 
-  // x2 in cell form over planes g*K .. g*K+K
+  // x2 in cell form: cell g spans node planes gK .. gK+K; zm/zq[0] is its left plane
   T zm[NP], zq[NP];
   T carry = T(0);
   zm[0] = zq[0] = T(0);
   if (g0 > 0) {
+    fetch((g0 - 1) * K, 1);
+    stage(1);
+    fetch((g0 - 1) * K + 1, K);
+    reduce(1);
+    zm[0] = Pm[tid];
+    zq[0] = Pq[tid];
+    __syncthreads();
+    stage(K);
+    fetch(g0 * K + 1, K);
+    reduce(K);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) plane((g0 - 1) * K + j, zm[j], zq[j]);
+    for (int j = 0; j < K; ++j) {
+      zm[1 + j] = Pm[j * TY * TX + tid];
+      zq[1 + j] = Pq[j * TY * TX + tid];
+    }
+    __syncthreads();
     const DevTables<T>& tb = gtab_fresh<T>(K);
 #pragma unroll
     for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
+  } else {
+    fetch(1, K);
   }
   for (long long g = g0; g < g1; ++g) {
+    stage(K);
+    if (g + 1 < g1) fetch((g + 1) * K + 1, K);
+    reduce(K);
 #pragma unroll
-    for (int j = 1; j < NP; ++j) plane(g * K + j, zm[j], zq[j]);
+    for (int j = 0; j < K; ++j) {
+      zm[1 + j] = Pm[j * TY * TX + tid];
+      zq[1 + j] = Pq[j * TY * TX + tid];
+    }
+    __syncthreads();
     const DevTables<T>& tb = gtab_fresh<T>(K);
 #pragma unroll
     for (int li = 0; li < K; ++li) {
@@ -692,128 +730,118 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
   }
 }
 
-// ----------------------------------------------- restriction, 3D streaming form
+// ------------------------------------------------- restriction, 3D in two kernels
 //
 // rc = (P1 x P1 x P1)^T rf in cell form: along each axis the fine nodes are split into
 // half-open runs 2KC .. 2KC + 2K - 1, one per coarse cell C, and each run maps to the K+1
 // coarse nodes of its cell with P[q][a] = phi_a(fine position q); a coarse vertex sums the
 // parts of its two cells (the fine node on the vertex lies in one run only, so every entry of
-// P1 is used once).  A workgroup owns a TX x TX tile of coarse columns and walks a
-// chunk of coarse cells along x2, reducing every fine plane in-plane (x0, then x1) and
-// accumulating the x2 part in registers, so the fine vector is read once and nothing is
-// staged in global memory.  Fine boundary nodes count as 0; coarse boundary nodes are
-// written 0.
+// P1 is used once).  Fine boundary nodes count as 0; coarse boundary nodes are written 0.
+//  * restrict_plane_kernel: one workgroup per (fine plane, TX x TX coarse-column tile) reduces
+//    the plane along x0 and x1 (LDS) into T[zf][J1][J0] (nc x nc per fine plane);
+//  * restrict_z_kernel: one thread per coarse node reduces T along x2.
+// Every launch is fully parallel (no chain of dependent planes inside a workgroup), the fine
+// vector is read once and the intermediate is a quarter of it.
 
 template <int K>
-struct ResStream {
-  static constexpr int CX = K == 1 ? 8 : K == 2 ? 4 : K == 3 ? 3 : K <= 5 ? 2 : 1;
-  static constexpr int TX = K * CX;                // coarse outputs per tile row
-  static constexpr int NT = TX * TX;               // one thread per coarse column
-  static constexpr int IX = 2 * TX + 2 * K;        // fine extent [2o - 2K, 2o + 2TX - 1]
+struct ResPlane {
+  static constexpr int CX = K == 1 ? 16 : K == 2 ? 8 : K == 3 ? 5 : K == 4 ? 4 : K == 5 ? 3 : 2;
+  static constexpr int TX = K * CX;            // coarse columns per tile row
+  static constexpr int NT = 256;
+  static constexpr int IX = 2 * TX + 2 * K;    // fine extent [2o - 2K, 2o + 2TX - 1]
 };
 
+// in[t] = fine nodes 2K(C-1) + t, t < 4K (the runs of cells C-1 and C): coarse node a of cell C
 template <int K, typename T>
-__global__ __launch_bounds__((ResStream<K>::NT)) void restrict_stream_kernel(const T* __restrict__ rf,
-                                                                            T* __restrict__ rc, long long nf,
-                                                                            long long nc, int tiles, int czc) {
-  using S = ResStream<K>;
-  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, NP = K + 1, RUN = 2 * K;
-  __shared__ T X[IX * IX];   // fine plane with halo, [r][c]
-  __shared__ T Rx[IX * TX];  // reduced along x0, [fine row][coarse col]
-  __shared__ T Pl[TX * TX];  // reduced along x0 and x1
+__device__ __forceinline__ T restrict_run(const DevTables<T>& tb, const T* in, int a) {
+  constexpr int NP = K + 1, RUN = 2 * K;
+  T s = T(0);
+  if (a == 0) {
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + K], in[q], s);
+  }
+#pragma unroll
+  for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + a], in[RUN + q], s);
+  return s;
+}
 
+template <int K, typename T>
+__global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict__ rf, T* __restrict__ tz,
+                                                            long long nf, long long nc, int tiles) {
+  using S = ResPlane<K>;
+  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, RUN = 2 * K;
+  __shared__ T X[IX * IX];
+  __shared__ T Rx[IX * TX];
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = blk % tiles;
-  const int ty = (blk / tiles) % tiles;
-  const int chunk = blk / (tiles * tiles);
-  const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;  // first coarse node of the tile
-  const long long ncz = (nc - 1) / K;                                // coarse cells along x2
-  const long long c0 = (long long)chunk * czc;
-  const long long c1 = c0 + czc < ncz ? c0 + czc : ncz;
-  const long long nf2 = nf * nf, nc2 = nc * nc;
+  const int tx = blk % tiles, ty = blk / tiles;
+  const long long zf = 1 + (long long)blockIdx.y;  // interior fine plane
+  const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;
+  const T* fz = rf + zf * nf * nf;
   const int tid = threadIdx.x;
-  const int px = tid % TX, py = tid / TX;
-  const long long gx = o0 + px, gy = o1 + py;
-  const bool col_valid = gx < nc && gy < nc;
-  const bool col_bnd = gx == 0 || gy == 0 || gx == nc - 1 || gy == nc - 1;
-
-  // in[t] = fine nodes 2K(C-1) + t, t < 4K: the runs of cells C-1 and C; output a of cell C
-  auto reduce = [](const DevTables<T>& tb, const T* in, int a) -> T {
-    T s = T(0);
-    if (a == 0) {
+  for (int i = tid; i < IX * IX; i += NT) {
+    const int r = i / IX, c = i - r * IX;
+    const long long fy = 2 * o1 - 2 * K + r, fx = 2 * o0 - 2 * K + c;
+    const bool ok = fy >= 1 && fy <= nf - 2 && fx >= 1 && fx <= nf - 2;
+    X[i] = ok ? fz[fy * nf + fx] : T(0);
+  }
+  __syncthreads();
+  for (int task = tid; task < IX * CX; task += NT) {
+    const DevTables<T>& tb = gtab_fresh<T>(K);
+    const int r = task / CX, cx = task - r * CX;
+    T in[2 * RUN];
 #pragma unroll
-      for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + K], in[q], s);
-    }
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * IX + RUN * cx + t];
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + a], in[RUN + q], s);
-    return s;
-  };
-
-  auto plane = [&](long long zf) -> T {
-    const bool zin = zf >= 1 && zf <= nf - 2;
-    const T* fz = rf + (zin ? zf : 0) * nf2;
-    for (int i = tid; i < IX * IX; i += NT) {
-      const int r = i / IX, c = i - r * IX;
-      const long long fy = 2 * o1 - 2 * K + r, fx = 2 * o0 - 2 * K + c;
-      const bool ok = zin && fy >= 1 && fy <= nf - 2 && fx >= 1 && fx <= nf - 2;
-      X[i] = ok ? fz[fy * nf + fx] : T(0);
-    }
-    __syncthreads();
-    for (int task = tid; task < IX * CX; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
-      const int r = task / CX, cx = task - r * CX;
-      T in[2 * RUN];
+    for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = restrict_run<K, T>(tb, in, a);
+  }
+  __syncthreads();
+  T* out = tz + zf * nc * nc;
+  for (int task = tid; task < TX * CX; task += NT) {
+    const DevTables<T>& tb = gtab_fresh<T>(K);
+    const int cy = task / TX, c = task - cy * TX;
+    T in[2 * RUN];
 #pragma unroll
-      for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * IX + RUN * cx + t];
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(RUN * cy + t) * TX + c];
+    const long long gx = o0 + c;
 #pragma unroll
-      for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = reduce(tb, in, a);
-    }
-    __syncthreads();
-    for (int task = tid; task < TX * CX; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
-      const int cy = task / TX, c = task - cy * TX;
-      T in[2 * RUN];
-#pragma unroll
-      for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(RUN * cy + t) * TX + c];
-#pragma unroll
-      for (int a = 0; a < K; ++a) Pl[(cy * K + a) * TX + c] = reduce(tb, in, a);
-    }
-    __syncthreads();
-    return Pl[tid];
-  };
-
-  // x2: coarse cell C owns fine planes 2KC .. 2KC + 2K - 1; its right-vertex part carries over
-  T carry = T(0);
-  if (c0 > 0) {
-#pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-      const T v = plane(RUN * (c0 - 1) + q);
-      const DevTables<T>& tb = gtab_fresh<T>(K);
-      carry = fma(tb.P[q * NP + K], v, carry);
+    for (int a = 0; a < K; ++a) {
+      const long long gy = o1 + cy * K + a;
+      if (gx < nc && gy < nc) out[gy * nc + gx] = restrict_run<K, T>(tb, in, a);
     }
   }
-  for (long long C = c0; C < c1; ++C) {
-    T acc[NP];
-#pragma unroll
-    for (int a = 0; a < NP; ++a) acc[a] = T(0);
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, long long nf,
+                                                        long long nc) {
+  constexpr int NP = K + 1, RUN = 2 * K;
+  const long long nc2 = nc * nc;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc2 * nc) return;
+  const long long zc = t / nc2, rem = t - zc * nc2;
+  const long long gy = rem / nc, gx = rem - gy * nc;
+  if (zc == 0 || zc == nc - 1 || gy == 0 || gy == nc - 1 || gx == 0 || gx == nc - 1) {
+    rc[t] = T(0);
+    return;
+  }
+  const DevTables<T>& tb = gtab<T>(K);
+  const long long C = zc / K;
+  const int a = (int)(zc - C * K);
+  const T* col = tz + rem;
+  T s = T(0);
+  if (a == 0) {
 #pragma unroll
     for (int q = 0; q < RUN; ++q) {
-      const T v = plane(RUN * C + q);
-      const DevTables<T>& tb = gtab_fresh<T>(K);
-#pragma unroll
-      for (int a = 0; a < NP; ++a) acc[a] = fma(tb.P[q * NP + a], v, acc[a]);
+      const long long zf = RUN * (C - 1) + q;  // >= 0 since zc > 0 means C >= 1 here
+      if (zf >= 1) s = fma(tb.P[q * NP + K], col[zf * nc2], s);
     }
-    if (col_valid) {
-#pragma unroll
-      for (int a = 0; a < K; ++a) {
-        const long long zc = K * C + a;
-        const T val = a == 0 ? acc[0] + carry : acc[a];
-        rc[zc * nc2 + gy * nc + gx] = (col_bnd || zc == 0) ? T(0) : val;
-      }
-    }
-    carry = acc[K];
   }
-  if (c1 == ncz && col_valid) rc[(nc - 1) * nc2 + gy * nc + gx] = T(0);
+#pragma unroll
+  for (int q = 0; q < RUN; ++q) {
+    const long long zf = RUN * C + q;
+    if (zf >= 1 && zf <= nf - 2) s = fma(tb.P[q * NP + a], col[zf * nc2], s);
+  }
+  rc[t] = s;
 }
 
 // ------------------------------------------------------- boundary and rhs
@@ -975,11 +1003,18 @@ constexpr bool kOpStream3D = false;  // cubic-tile operator in 3D as well (compa
 #else
 constexpr bool kOpStream3D = true;
 #endif
+#ifndef VPS_OP_STREAM_MIN_CELLS
+#define VPS_OP_STREAM_MIN_CELLS 64
+#endif
+constexpr long long kOpStreamMinCells = VPS_OP_STREAM_MIN_CELLS;
 
 template <int D, int K, typename T>
 hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
   if constexpr (D == 3 && kOpStream3D) {
-    return op_stream_launch<K, T>(g, x, b, y, st);
+    // small levels have too few column tiles to hide the plane-to-plane chain of the streaming
+    // kernel: the cubic tiles run fully in parallel there
+    if (g.ncells >= kOpStreamMinCells) return op_stream_launch<K, T>(g, x, b, y, st);
+    return op_tile_launch<D, K, T>(g, x, b, y, st);
   } else {
     return op_tile_launch<D, K, T>(g, x, b, y, st);
   }
@@ -998,9 +1033,9 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
 }
 
 #ifdef VPS_RES_PASSES_3D
-constexpr bool kResStream3D = false;  // separable passes in 3D as well (comparison builds)
+constexpr bool kResPlane3D = false;  // three separable passes in 3D as well (comparison builds)
 #else
-constexpr bool kResStream3D = true;
+constexpr bool kResPlane3D = true;
 #endif
 
 template <int D, int K, typename T>
@@ -1013,19 +1048,15 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
   };
   if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
     return hipErrorInvalidConfiguration;
-  if (D == 3 && kResStream3D) {
-    using S = ResStream<K>;
+  if (D == 3 && kResPlane3D) {
+    using S = ResPlane<K>;
     const int tiles = ceil_div(nc, S::TX);
-    const long long ncz = (nc - 1) / K;
-    long long chunks = (2048 + (long long)tiles * tiles - 1) / ((long long)tiles * tiles);
-    if (chunks > ncz / 2) chunks = ncz / 2;
-    if (chunks < 1) chunks = 1;
-    const int czc = (int)((ncz + chunks - 1) / chunks);
-    chunks = (ncz + czc - 1) / czc;
-    const long long blocks = (long long)tiles * tiles * chunks;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((restrict_stream_kernel<K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)rf,
-                       (T*)rc, (long long)nf, (long long)nc, tiles, czc);
+    if ((long long)tiles * tiles > 0x7fffffffLL || nf - 2 > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)(nf - 2)), dim3(S::NT),
+                       0, st, (const T*)rf, (T*)t1, (long long)nf, (long long)nc, tiles);
+    const long long ntot = (long long)nc * nc * nc;
+    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
+                       (const T*)t1, (T*)rc, (long long)nf, (long long)nc);
   } else if (D == 2) {
     // x0: [nf][nf] -> T1 [nf][nc]; x1: T1 -> rc [nc][nc]
     hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, 1), dim3(256), 0, st, (const T*)rf,

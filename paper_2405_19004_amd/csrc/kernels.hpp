@@ -85,8 +85,12 @@ hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, 
                                      double* out, int* bad, hipStream_t st);
 hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, long long n,
                        double* partial, double* out, hipStream_t st);
+// x += alpha p, r -= alpha q, partials of r.r and r.z; also r32 = (float) r when r32 != null
 hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
-                            double* sc, double* partial, hipStream_t st);
+                            double* sc, double* partial, float* r32, hipStream_t st);
+// z = (double) z32 and out[0] = r.z (deterministic)
+hipError_t launch_widen_dot(const float* z32, double* z, const double* r, long long n, double* partial, double* out,
+                            hipStream_t st);
 hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st);
 hipError_t launch_cg_direction(double* p, const double* z, long long n, const double* sc, hipStream_t st);
 

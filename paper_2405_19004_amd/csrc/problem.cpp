@@ -380,17 +380,21 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
 
 // ------------------------------------------------------------------------ CG
 
-Status precondition(Problem* p, int mode, const double* r, double* z) {
+// z = M r with the problem's CG vectors, and sc[RZNew] = r.z.  Mixed mode: the FP32 copy of r
+// must already be in the level-L FP32 rhs (cg_update or pcg_begin writes it); the widening of
+// the FP32 result is fused with the dot product.
+Status precondition(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
   if (mode == 0) {
-    VPS_HIP(launch_fill(0, z, N, 0.0, p->stream));
-    return vcycle(p, 0, r, z);
+    VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
+    VPS_TRY(vcycle(p, 0, p->r, p->z));
+    VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
+    return Status::ok();
   }
   LevelBuffers& B = p->lv[p->L];
-  VPS_HIP(launch_cast(0, r, B.b[1], N, p->stream));
   VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
   VPS_TRY(vcycle(p, 1, B.b[1], B.x[1]));
-  VPS_HIP(launch_cast(1, B.x[1], z, N, p->stream));
+  VPS_HIP(launch_widen_dot((const float*)B.x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew, p->stream));
   return Status::ok();
 }
 
@@ -407,18 +411,21 @@ Status precondition_group(Problem* const* ps, int n, int mode) {
       xs[i] = p->z;
     } else {
       LevelBuffers& B = p->lv[p->L];
-      VPS_HIP(launch_cast(0, p->r, B.b[1], N, p->stream));
       VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
       bs[i] = B.b[1];
       xs[i] = B.x[1];
     }
   }
   VPS_TRY(vcycle_group(ps, n, prec, bs.data(), xs.data()));
-  if (mode != 0)
-    for (int i = 0; i < n; ++i) {
-      Problem* p = ps[i];
-      VPS_HIP(launch_cast(1, p->lv[p->L].x[1], p->z, p->lv[p->L].N, p->stream));
-    }
+  for (int i = 0; i < n; ++i) {
+    Problem* p = ps[i];
+    const long long N = p->lv[p->L].N;
+    if (mode == 0)
+      VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
+    else
+      VPS_HIP(launch_widen_dot((const float*)p->lv[p->L].x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew,
+                               p->stream));
+  }
   return Status::ok();
 }
 
@@ -444,8 +451,8 @@ Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) 
     cs->stats.rel_residual = 0.0;
     return Status::ok();
   }
-  VPS_TRY(precondition(p, mode, p->r, p->z));
-  VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
+  if (mode == 1) VPS_HIP(launch_cast(0, p->r, p->lv[p->L].b[1], N, p->stream));
+  VPS_TRY(precondition(p, mode));
   VPS_HIP(launch_cg_beta(p->sc, 0, p->stream));  // rz <- rz_new (beta unused here)
   VPS_HIP(hipMemcpyAsync(p->p, p->z, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   return Status::ok();
@@ -456,7 +463,8 @@ Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
   const long long N = p->lv[p->L].N;
   VPS_HIP(launch_operator(p->geom(p->L), 0, p->p, nullptr, p->q, p->stream));
   VPS_HIP(launch_dot2(p->p, p->q, nullptr, nullptr, N, p->partial, p->sc + kScPQ, p->stream));
-  VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, N, p->sc, p->partial, p->stream));
+  float* r32 = mode == 1 ? static_cast<float*>(p->lv[p->L].b[1]) : nullptr;  // input of the FP32 V-cycle
+  VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, N, p->sc, p->partial, r32, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   (void)cs;
   return Status::ok();
@@ -486,7 +494,6 @@ Status pcg_decide(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
 
 Status pcg_after_precond(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
-  VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
   // flexible (Polak-Ribiere) beta whenever the preconditioner is not symmetric: FP32 V-cycle
   // (rounding) or the literal colour order after the coarse correction
   VPS_HIP(launch_cg_beta(p->sc, (mode == 1 || p->post_same_order) ? 1 : 0, p->stream));
@@ -497,7 +504,7 @@ Status pcg_after_precond(Problem* p, int mode) {
 Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs) {
   VPS_TRY(pcg_decide(p, mode, rtol, maxit, cs));
   if (cs->done) return Status::ok();
-  VPS_TRY(precondition(p, mode, p->r, p->z));
+  VPS_TRY(precondition(p, mode));
   return pcg_after_precond(p, mode);
 }
 

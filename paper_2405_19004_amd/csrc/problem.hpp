@@ -95,10 +95,11 @@ Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs);   // en
 Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync: decide, enqueue precond
 // pcg_iterate_finish in parts, for callers that precondition several problems together:
 Status pcg_decide(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync; no launches
-Status pcg_after_precond(Problem* p, int mode);  // z is ready: r.z, beta, new direction
-// z = M r (FP64 V-cycle, or FP32 V-cycle between casts) for one problem / a group (same dim, degree)
-Status precondition(Problem* p, int mode, const double* r, double* z);
-Status precondition_group(Problem* const* ps, int n, int mode);  // z_i = M r_i with each problem's CG vectors
+Status pcg_after_precond(Problem* p, int mode);  // z and r.z are ready: beta, new direction
+// z = M r and r.z with the CG vectors (FP64 V-cycle, or FP32 V-cycle on the FP32 copy of r that
+// cg_update / pcg_begin wrote, widened back) for one problem / a group (same dim, degree)
+Status precondition(Problem* p, int mode);
+Status precondition_group(Problem* const* ps, int n, int mode);
 Status pcg_end(Problem* p, const double* b, double* x, CgState* cs);
 
 }  // namespace vps

@@ -59,16 +59,28 @@ template <int K> struct SmootherShape<3, K> {
   static constexpr int NT = K == 4 ? VPS_Q4_3D_NT : K <= 5 ? 128 : K == 6 ? 192 : 256;
 };
 
+// Patches per workgroup for small launches (coarse levels): fewer patches per workgroup means
+// fewer tasks per thread in every stage, so a workgroup finishes sooner; used when the default
+// shape would give fewer than kLatencyBlocks workgroups, where the chip is not full anyway.
+template <int D, int K>
+struct LatencyPPW {
+  static constexpr int value = D == 3 ? (K == 1 ? 8 : K == 2 ? 2 : 1) : (K == 1 ? 16 : K == 2 ? 8 : K <= 5 ? 4 : 2);
+};
+#ifndef VPS_LATENCY_BLOCKS
+#define VPS_LATENCY_BLOCKS 1024
+#endif
+constexpr long long kLatencyBlocks = VPS_LATENCY_BLOCKS;
+
 // Smallest s >= v with s = r (mod 32): padded outer strides of the LDS transpose buffers.
 constexpr int pad32(int v, int r) { return v + ((r - v) % 32 + 32) % 32; }
 
 // LDS layouts.  Every transpose buffer puts the loop axis of the stage that reads it outermost,
 // so the reading lanes touch consecutive words; the outer stride is padded (mod 32) so that the
 // writing lanes of the previous stage also fall into distinct banks.
-template <int D, int K, typename T, bool ADD>
+template <int D, int K, typename T, bool ADD, int PPWv>
 struct SmootherLds {
   static constexpr int n = 2 * K + 1, m = 2 * K - 1;
-  static constexpr int PPW = SmootherShape<D, K>::PPW;
+  static constexpr int PPW = PPWv;
   static constexpr int RS = 2 * K * PPW + 1;  // closure row segment of the workgroup
   // ---- 3D strides
   // residue of the P stride that makes the x0-contraction writes conflict-free (searched per degree
@@ -114,14 +126,14 @@ __device__ __forceinline__ const DevTables<T>& tab_fresh(int k) {
 
 // One workgroup's share of a colour pass: patches of block `blk` of the colour described by
 // (p0, p1, p2, cnt0, cnt1, groups0) on a level with n1d nodes per direction.
-template <int D, int K, typename T, int MODE>
+template <int D, int K, typename T, int MODE, int PPW>
 __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T* __restrict__ b, T* __restrict__ x,
                                                   long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
                                                   int groups0, T res_scale, T sol_scale, unsigned blk) {
   constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
-  constexpr int PPW = SmootherShape<D, K>::PPW, NT = SmootherShape<D, K>::NT;
+  constexpr int NT = SmootherShape<D, K>::NT;
   constexpr bool ADD = MODE == kModeAdditive, BND = MODE == kModeBoundary;
-  using L = SmootherLds<D, K, T, ADD>;
+  using L = SmootherLds<D, K, T, ADD, PPW>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
@@ -552,12 +564,12 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
   }
 }
 
-template <int D, int K, typename T, int MODE>
+template <int D, int K, typename T, int MODE, int PPW>
 __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
     const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
     int groups0, T res_scale, T sol_scale) {
-  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive>::total];
-  colour_pass_block<D, K, T, MODE>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
+  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive, PPW>::total];
+  colour_pass_block<D, K, T, MODE, PPW>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
                                   xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -565,12 +577,13 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
 // levels in one launch: entry e owns blocks [begin[e], begin[e+1]).
 template <int D, int K, typename T, int MODE>
 __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_group_kernel(ColourPassGroup grp) {
-  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive>::total];
+  constexpr int PPW = SmootherShape<D, K>::PPW;
+  __shared__ T smem[SmootherLds<D, K, T, MODE == kModeAdditive, PPW>::total];
   const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
   int e = 0;
   while (e + 1 < grp.n && (unsigned)grp.e[e + 1].block_begin <= g) ++e;
   const ColourPassDesc& d = grp.e[e];
-  colour_pass_block<D, K, T, MODE>(smem, (const T*)d.b, (T*)d.x, d.n1d, d.p[0], d.p[1], d.p[2], d.cnt0, d.cnt1,
+  colour_pass_block<D, K, T, MODE, PPW>(smem, (const T*)d.b, (T*)d.x, d.n1d, d.p[0], d.p[1], d.p[2], d.cnt0, d.cnt1,
                                   d.groups0, (T)d.res_scale, (T)d.sol_scale, g - (unsigned)d.block_begin);
 }
 
@@ -583,8 +596,7 @@ struct ColourGrid {
   int groups0 = 0;
   long long blocks = 0;
   bool ok = true;  // the 32-bit block offsets of the kernel are valid
-  ColourGrid(const LevelGeom& g, int colour) {
-    constexpr int PPW = SmootherShape<D, K>::PPW;
+  ColourGrid(const LevelGeom& g, int colour, int PPW = SmootherShape<D, K>::PPW) {
     const int half = (int)(g.ncells / 2);
     for (int a = 0; a < D; ++a) {
       p[a] = (colour >> a) & 1;
@@ -600,18 +612,33 @@ struct ColourGrid {
   }
 };
 
-template <int D, int K, typename T, int MODE>
-static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
+template <int D, int K, typename T, int MODE, int PPW>
+static hipError_t launch_shape(const LevelGeom& g, const ColourGrid<D, K>& cg, const void* b, void* x,
+                               hipStream_t st) {
   constexpr int NT = SmootherShape<D, K>::NT;
-  const ColourGrid<D, K> cg(g, colour);
-  if (!cg.ok) return hipErrorInvalidConfiguration;
-  if (cg.blocks == 0) return hipSuccess;
   // Abar_h = h^(d-2) Abar_1 ; A_j,h^{-1} = h^(2-d) A_j,1^{-1}
   const T res_scale = (T)(D == 3 ? g.h : 1.0);
   const T sol_scale = (T)(D == 3 ? 1.0 / g.h : 1.0);
-  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, MODE>), dim3((unsigned)cg.blocks), dim3(NT), 0, st, (const T*)b,
-                     (T*)x, g.n1d, cg.p[0], cg.p[1], cg.p[2], cg.cnt[0], cg.cnt[1], cg.groups0, res_scale, sol_scale);
+  hipLaunchKernelGGL((colour_pass_kernel<D, K, T, MODE, PPW>), dim3((unsigned)cg.blocks), dim3(NT), 0, st,
+                     (const T*)b, (T*)x, g.n1d, cg.p[0], cg.p[1], cg.p[2], cg.cnt[0], cg.cnt[1], cg.groups0,
+                     res_scale, sol_scale);
   return hipGetLastError();
+}
+
+template <int D, int K, typename T, int MODE>
+static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
+  constexpr int PPW = SmootherShape<D, K>::PPW, LPPW = LatencyPPW<D, K>::value;
+  const ColourGrid<D, K> cg(g, colour);
+  if (!cg.ok) return hipErrorInvalidConfiguration;
+  if (cg.blocks == 0) return hipSuccess;
+  if constexpr (LPPW < PPW) {
+    if (cg.blocks < kLatencyBlocks) {
+      const ColourGrid<D, K> cl(g, colour, LPPW);
+      if (!cl.ok) return hipErrorInvalidConfiguration;
+      return launch_shape<D, K, T, MODE, LPPW>(g, cl, b, x, st);
+    }
+  }
+  return launch_shape<D, K, T, MODE, PPW>(g, cg, b, x, st);
 }
 
 template <int D, int K, typename T, int MODE>

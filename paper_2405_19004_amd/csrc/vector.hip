@@ -98,19 +98,35 @@ __global__ void finalize1_kernel(const double* __restrict__ partial, int nparts,
 
 // CG step: x += alpha p, r -= alpha q, with alpha = s[RZ] / s[PQ];
 // partials of r.r (slot 0) and r.z (slot 1, z = the previous preconditioned residual).
+// With r32 != null the updated residual is also stored rounded to FP32 (the input of the FP32
+// preconditioner), which saves a separate cast pass.
 __global__ void cg_update_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                                  const double* __restrict__ q, const double* __restrict__ z, long long n,
-                                 const double* __restrict__ sc, double* __restrict__ partial) {
+                                 const double* __restrict__ sc, double* __restrict__ partial, float* __restrict__ r32) {
   const double alpha = sc[kScRZ] / sc[kScPQ];
   double s0 = 0.0, s1 = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
+    if (r32) r32[i] = (float)ri;
     s0 = fma(ri, ri, s0);
     s1 = fma(ri, z[i], s1);
   }
   block_reduce2(s0, s1, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
+}
+
+// z = (double) z32 and partials of r.z: the widening of the FP32 preconditioner output fused
+// with the dot product CG takes next.
+__global__ void widen_dot_kernel(const float* __restrict__ z32, double* __restrict__ z, const double* __restrict__ r,
+                                 long long n, double* __restrict__ partial) {
+  double s0 = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double zi = (double)z32[i];
+    z[i] = zi;
+    s0 = fma(r[i], zi, s0);
+  }
+  block_reduce2(s0, 0.0, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
 }
 
 // p = z + beta p, beta from the scalar block
@@ -177,10 +193,18 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, const 
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
-                            double* sc, double* partial, hipStream_t st) {
+hipError_t launch_widen_dot(const float* z32, double* z, const double* r, long long n, double* partial, double* out,
+                            hipStream_t st) {
   const int parts = reduction_parts();
-  hipLaunchKernelGGL(cg_update_kernel, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z, n, sc, partial);
+  hipLaunchKernelGGL(widen_dot_kernel, dim3(parts), dim3(kRedThreads), 0, st, z32, z, r, n, partial);
+  hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
+                            double* sc, double* partial, float* r32, hipStream_t st) {
+  const int parts = reduction_parts();
+  hipLaunchKernelGGL(cg_update_kernel, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z, n, sc, partial, r32);
   hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, sc + kScRR);
   return hipGetLastError();
 }
