@@ -349,7 +349,7 @@ def main():
             traffic = rec.get("bytes_per_launch")
     out["roofline"] = {"bound": "alu", "achieved": flops / t_all / 1e12, "peak": PEAK_FP32 / 1e12,
                        "unit": "TFLOP/s", "frac": flops / t_all / PEAK_FP32, "traffic": traffic,
-                       "kernel": "colour_pass_kernel<3,4,float,false>", "avg_launch_us": 1e6 * t_all,
+                       "kernel": "colour_pass_kernel<3,4,float,multiplicative,2 patches per workgroup>", "avg_launch_us": 1e6 * t_all,
                        "algorithmic_bytes_per_launch": bytes_, "algorithmic_gbps": bytes_ / t_all / 1e9,
                        "flops_per_launch": flops, "launches_timed": launches}
     xz = torch.zeros_like(b)
