@@ -33,13 +33,18 @@ PEAK_FP64 = 78.6e12
 
 
 def colour_pass_flops(d, k):
-    """Algorithmic flops of one patch (interior-row residual with reuse + FD solve + update)."""
+    """Algorithmic flops of one patch: interior-row residual by sum factorisation with reuse,
+    FD solve (S^T, eigenvalue scaling, S per direction) and update.  The 1D patch rows have
+    nnz = (2k-2)(k+1) + (2k+1) structural nonzeros (a cell-interior node couples to its cell's
+    k+1 nodes, the middle vertex to all 2k+1); products with structural zeros are not counted."""
     n, m = 2 * k + 1, 2 * k - 1
+    nnz = (2 * k - 2) * (k + 1) + (2 * k + 1)
     if d == 3:
-        macs = 2 * n ** 3 * m + 3 * n ** 2 * m ** 2 + 2 * n * m ** 3 + 6 * m ** 4
+        macs = (2 * nnz * n * n + 3 * nnz * n * m + m * m * (2 * nnz + m + m * m)
+                + m ** 4 + m * m * (2 * m * m + m) + 2 * m ** 4 + m ** 3)
     else:
-        macs = 2 * n ** 2 * m + 2 * n * m ** 2 + 4 * m ** 3
-    return 2 * macs + 3 * m ** d
+        macs = 2 * nnz * n + m * (2 * nnz + m + m * m) + m * (2 * m * m + m) + m * m * m + m * m
+    return 2 * macs
 
 
 def colour_pass_bytes(d, k, es):

@@ -193,11 +193,14 @@ Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const 
   return Status::ok();
 }
 
-Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x) {
+Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x, bool x_zero) {
   const int nc = 1 << p->dim;
   for (int i = 0; i < nc; ++i) {
     const int c = reverse ? nc - 1 - i : i;
-    VPS_TRY(colour_pass(p, level, prec, mode, c, b, x));
+    // on x = 0 the first multiplicative colour reduces to x^I = A_j^{-1} b^I (residual = b,
+    // x^B = 0): the additive kernel gives the same values without forming the residual
+    const int m = (i == 0 && x_zero && mode != kModeAdditive) ? kModeAdditive : mode;
+    VPS_TRY(colour_pass(p, level, prec, m, c, b, x));
   }
   return Status::ok();
 }
@@ -218,7 +221,7 @@ Status coarse_solve(Problem* p, int prec, const void* b, void* x) {
   return Status::ok();
 }
 
-Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT) {
+Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT, bool top_zero) {
   if (!p->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
   if (top == 1) return coarse_solve(p, prec, bT, xT);
   const bool post_rev = !p->post_same_order;
@@ -227,7 +230,7 @@ Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT) {
     const void* b = lvl == top ? bT : p->lv[lvl].b[prec];
     void* x = lvl == top ? xT : p->lv[lvl].x[prec];
     if (lvl < top) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
-    VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), false, b, x));
+    VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), false, b, x, lvl < top || top_zero));
     VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
     VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
                             p->lv[lvl].t2[prec], p->stream));
@@ -243,7 +246,7 @@ Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT) {
   return Status::ok();
 }
 
-Status vcycle(Problem* p, int prec, const void* bL, void* xL) { return vcycle_top(p, prec, p->L, bL, xL); }
+Status vcycle(Problem* p, int prec, const void* bL, void* xL) { return vcycle_top(p, prec, p->L, bL, xL, false); }
 
 // ------------------------------------------------------------------------ FMG
 
@@ -305,7 +308,7 @@ Status fmg(Problem* p, int prec, const void* const* b_levels, void* x, double ep
   for (int lvl = 2; lvl <= L; ++lvl) {
     VPS_HIP(launch_fill(prec, level_x(lvl), p->lv[lvl].N, 0.0, p->stream));
     VPS_HIP(launch_prolongate_add(p->geom(lvl), prec, level_x(lvl - 1), level_x(lvl), p->stream));
-    VPS_TRY(vcycle_top(p, prec, lvl, b_levels[lvl - 1], level_x(lvl)));
+    VPS_TRY(vcycle_top(p, prec, lvl, b_levels[lvl - 1], level_x(lvl), false));
   }
   VPS_TRY(residual_norm2(p, prec, b_levels[L - 1], x, p->sc + kScTrue));
   VPS_TRY(fetch_scalars(p));
@@ -318,7 +321,7 @@ Status fmg(Problem* p, int prec, const void* const* b_levels, void* x, double ep
   double delta = std::sqrt(p->host_sc[kScTrue]);
   // further V-cycles on the finest level until the residual has dropped by eps
   while (std::isfinite(delta) && delta > eps * d0 && st.iterations < maxit) {
-    VPS_TRY(vcycle_top(p, prec, L, b_levels[L - 1], x));
+    VPS_TRY(vcycle_top(p, prec, L, b_levels[L - 1], x, false));
     VPS_TRY(residual_norm2(p, prec, b_levels[L - 1], x, p->sc + kScTrue));
     VPS_TRY(fetch_scalars(p));
     delta = std::sqrt(p->host_sc[kScTrue]);
@@ -330,7 +333,7 @@ Status fmg(Problem* p, int prec, const void* const* b_levels, void* x, double ep
   return Status::ok();
 }
 
-Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL) {
+Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL, bool top_zero) {
   if (n <= 0) return Status::ok();
   int Lmax = 0;
   for (int i = 0; i < n; ++i) {
@@ -346,20 +349,22 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
   auto level_b = [&](int i, int lvl) -> const void* { return lvl == ps[i]->L ? bL[i] : ps[i]->lv[lvl].b[prec]; };
   auto level_x = [&](int i, int lvl) -> void* { return lvl == ps[i]->L ? xL[i] : ps[i]->lv[lvl].x[prec]; };
   std::vector<ColourPassMember> mem;
-  auto smooth = [&](int lvl, bool reverse) -> Status {
+  // x_zero: every member's x is 0 on entry (the first colour then needs no residual, as in smoother())
+  auto smooth = [&](int lvl, bool reverse, bool x_zero) -> Status {
     mem.clear();
     for (int i = 0; i < n; ++i)
       if (ps[i]->L >= lvl) mem.push_back({ps[i]->geom(lvl), level_b(i, lvl), level_x(i, lvl)});
     for (int j = 0; j < nc; ++j) {
       const int c = reverse ? nc - 1 - j : j;
-      VPS_HIP(launch_colour_pass_group(dim, k, prec, vcycle_mode(ps[0]), c, mem.data(), (int)mem.size(), st));
+      const int mode = (j == 0 && x_zero) ? kModeAdditive : vcycle_mode(ps[0]);
+      VPS_HIP(launch_colour_pass_group(dim, k, prec, mode, c, mem.data(), (int)mem.size(), st));
     }
     return Status::ok();
   };
   for (int lvl = Lmax; lvl >= 2; --lvl) {
     for (int i = 0; i < n; ++i)
       if (ps[i]->L > lvl) VPS_HIP(launch_fill(prec, level_x(i, lvl), ps[i]->lv[lvl].N, 0.0, st));
-    VPS_TRY(smooth(lvl, false));
+    VPS_TRY(smooth(lvl, false, top_zero));  // levels below a member's top start from 0
     for (int i = 0; i < n; ++i) {
       if (ps[i]->L < lvl) continue;
       Problem* p = ps[i];
@@ -373,7 +378,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
     for (int i = 0; i < n; ++i)
       if (ps[i]->L >= lvl)
         VPS_HIP(launch_prolongate_add(ps[i]->geom(lvl), prec, ps[i]->lv[lvl - 1].x[prec], level_x(i, lvl), st));
-    VPS_TRY(smooth(lvl, post_rev));
+    VPS_TRY(smooth(lvl, post_rev, false));
   }
   return Status::ok();
 }
@@ -387,13 +392,13 @@ Status precondition(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
   if (mode == 0) {
     VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
-    VPS_TRY(vcycle(p, 0, p->r, p->z));
+    VPS_TRY(vcycle_top(p, 0, p->L, p->r, p->z, true));
     VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
     return Status::ok();
   }
   LevelBuffers& B = p->lv[p->L];
   VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
-  VPS_TRY(vcycle(p, 1, B.b[1], B.x[1]));
+  VPS_TRY(vcycle_top(p, 1, p->L, B.b[1], B.x[1], true));
   VPS_HIP(launch_widen_dot((const float*)B.x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew, p->stream));
   return Status::ok();
 }
@@ -416,7 +421,7 @@ Status precondition_group(Problem* const* ps, int n, int mode) {
       xs[i] = B.x[1];
     }
   }
-  VPS_TRY(vcycle_group(ps, n, prec, bs.data(), xs.data()));
+  VPS_TRY(vcycle_group(ps, n, prec, bs.data(), xs.data(), true));
   for (int i = 0; i < n; ++i) {
     Problem* p = ps[i];
     const long long N = p->lv[p->L].N;

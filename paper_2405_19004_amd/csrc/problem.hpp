@@ -60,17 +60,18 @@ size_t footprint_bytes(int dim, int degree, int L, unsigned flags);
 Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Problem** out);
 
 // Device steps (asynchronous on p->stream).
-Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x);
+// x_zero: x is 0 on entry (the first colour then runs the additive kernel, same values)
+Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const void* b, void* x, bool x_zero = false);
 Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x);
 Status coarse_solve(Problem* p, int prec, const void* b, void* x);
 Status vcycle(Problem* p, int prec, const void* b, void* x);
 // V-cycle with `top` as its finest level: b, x live on level `top`, levels below use the
-// hierarchy's buffers (top < L leaves levels above untouched).
-Status vcycle_top(Problem* p, int prec, int top, const void* b, void* x);
+// hierarchy's buffers (top < L leaves levels above untouched).  top_zero: x is 0 on entry.
+Status vcycle_top(Problem* p, int prec, int top, const void* b, void* x, bool top_zero);
 // V-cycles of n problems of the same (dim, degree), all on one stream, in lockstep: every colour
 // pass of a level is one packed launch over the problems that have that level.  Each problem's
 // arithmetic (and result) is exactly that of vcycle() on it alone.
-Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL);
+Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, void* const* xL, bool top_zero);
 
 struct SolveStats {
   int iterations = 0;

@@ -28,6 +28,7 @@
 // No atomics: patches of one colour write disjoint interiors.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "patch_tables_gen.hpp"
 
 namespace vps {
 
@@ -133,6 +134,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
   constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
   constexpr int NT = SmootherShape<D, K>::NT;
   constexpr bool ADD = MODE == kModeAdditive, BND = MODE == kModeBoundary;
+  // patch matrices and eigenvectors as compile-time constants (instruction literals / SGPR moves)
+  using PT = gen::PatchTables<T, K>;
   using L = SmootherLds<D, K, T, ADD, PPW>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
@@ -159,12 +162,13 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
   const T* bo = b + origin;
 
   // Lines along the slowest axis, task = (q, i1, i0) in 3D / (q, i0) in 2D with i0 fastest:
-  // the residual stage reads b on them and the last stage updates x^I on them.  Both are
-  // prefetched now (clamped to a valid patch so the loads are always in bounds).
+  // the residual stage reads b on them and the last stage updates x^I on them.  b is
+  // prefetched now (clamped to a valid patch so the loads are always in bounds); the old x^I
+  // comes from the closure in LDS in multiplicative mode and from global memory in additive mode.
   constexpr int NB = D == 3 ? PPW * mm : PPW * m;
   constexpr int RB = (NB + NT - 1) / NT;
   T bpre[RB][m], xpre[RB][m];
-  int loff[RB];
+  int loff[RB], xoff[RB];
 #pragma unroll
   for (int rr = 0; rr < RB; ++rr) {
     const int task = rr * NT + tid;
@@ -181,10 +185,11 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
     q = min(q, P - 1);
     const int off = (D == 3 ? ld2 + (1 + i1) * ld1 : ld1) + 2 * K * q + 1 + i0;
     loff[rr] = off;
+    xoff[rr] = (D == 3 ? (n + 1 + i1) * RS : RS) + 2 * K * q + 1 + i0;  // node (i=0) in the LDS closure
     const int st = D == 3 ? ld2 : ld1;
 #pragma unroll
     for (int i = 0; i < m; ++i) bpre[rr][i] = bo[off + i * st];
-    if constexpr (!BND) {
+    if constexpr (ADD) {
 #pragma unroll
       for (int i = 0; i < m; ++i) xpre[rr][i] = xo[off + i * st];
     }
@@ -229,6 +234,14 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       }
     }
     __syncthreads();
+    if constexpr (!BND) {
+      // old x^I of this thread's lines: patch-interior nodes are never Dirichlet nodes
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+        for (int i = 0; i < m; ++i) xpre[rr][i] = X[xoff[rr] + i * (D == 3 ? n * RS : RS)];
+      }
+    }
   }
 
   if constexpr (D == 3) {
@@ -243,7 +256,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         const int q = task / (n * n), r = task - q * (n * n);
         const int j2 = r / n, j1 = r - j2 * n;
         if (task < PPW * n * n && q < P) {
-          const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[(j2 * n + j1) * RS + 2 * K * q + j];
@@ -252,14 +264,14 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
+            for (int j = 0; j < n; ++j) sm = fma(PT::Mc[i * n + j], in[j], sm);
             PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
+            for (int j = 0; j < n; ++j) sa = fma(PT::Ac[i * n + j], in[j], sa);
             PA[o + i] = sa;
           }
         }
@@ -273,7 +285,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         const int q = task / (n * m), r = task - q * (n * m);
         const int j2 = r / m, i0 = r - j2 * m;
         if (task < PPW * n * m && q < P) {
-          const DevTables<T>& tb = tab_fresh<T>(K);
           T pm[n], pa[n];
           const int ri = task;  // = (q * n + j2) * m + i0
 #pragma unroll
@@ -287,9 +298,9 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             T su = T(0), sv = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              su = fma(tb.Mc[i * n + j], pm[j], su);
-              sv = fma(tb.Ac[i * n + j], pm[j], sv);
-              sv = fma(tb.Mc[i * n + j], pa[j], sv);
+              su = fma(PT::Mc[i * n + j], pm[j], su);
+              sv = fma(PT::Ac[i * n + j], pm[j], sv);
+              sv = fma(PT::Mc[i * n + j], pa[j], sv);
             }
             U[o + i * m] = su;
             V[o + i * m] = sv;
@@ -306,7 +317,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int q = task / mm, r = task - q * mm;
       const int i1 = r / m, i0 = r - i1 * m;
       if (task < NB && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T res[m];
         if constexpr (ADD) {
 #pragma unroll
@@ -325,8 +335,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             T s = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              s = fma(tb.Ac[i * n + j], u[j], s);
-              s = fma(tb.Mc[i * n + j], v[j], s);
+              s = fma(PT::Ac[i * n + j], u[j], s);
+              s = fma(PT::Mc[i * n + j], v[j], s);
             }
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
@@ -336,7 +346,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
+          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], res[i], s);
           W4[o + a * m] = s;
         }
       }
@@ -349,7 +359,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int q = task / mm, r = task - q * mm;
       const int a2 = r / m, i0 = r - a2 * m;
       if (task < PPW * mm && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W4[i * SI1 + task];
@@ -358,7 +367,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
+          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
           W5[o + a] = s;
         }
       }
@@ -380,7 +389,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
+          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
           z[a] = s * tb.inv3[li + a];
         }
         const int o = a1 * SA1 + q * mm + a2 * m;
@@ -388,7 +397,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
+          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], z[a], s);
           W6[o + i] = s;
         }
       }
@@ -401,7 +410,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int q = task / mm, r = task - q * mm;
       const int a2 = r / m, i0 = r - a2 * m;
       if (task < PPW * mm && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W6[a * SA1 + task];
@@ -410,7 +418,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
+          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
           W7[o + i * m] = s;
         }
       }
@@ -422,7 +430,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int task = rr * NT + tid;
       const int q = task / mm;
       if (task < NB && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W7[a * SA2 + task];
@@ -430,7 +437,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
+          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
           xo[loff[rr] + i * ld2] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
         }
       }
@@ -447,7 +454,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         const int task = base + tid;
         const int j1 = task / PPW, q = task - j1 * PPW;
         if (task < PPW * n && q < P) {
-          const DevTables<T>& tb = tab_fresh<T>(K);
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[j1 * RS + 2 * K * q + j];
@@ -456,14 +462,14 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sm = fma(tb.Mc[i * n + j], in[j], sm);
+            for (int j = 0; j < n; ++j) sm = fma(PT::Mc[i * n + j], in[j], sm);
             PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sa = fma(tb.Ac[i * n + j], in[j], sa);
+            for (int j = 0; j < n; ++j) sa = fma(PT::Ac[i * n + j], in[j], sa);
             PA[o + i] = sa;
           }
         }
@@ -478,7 +484,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int task = rr * NT + tid;
       const int q = task / m, i0 = task - q * m;
       if (task < NB && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T res[m];
         if constexpr (ADD) {
 #pragma unroll
@@ -497,8 +502,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             T s = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              s = fma(tb.Ac[i * n + j], pm[j], s);
-              s = fma(tb.Mc[i * n + j], pa[j], s);
+              s = fma(PT::Ac[i * n + j], pm[j], s);
+              s = fma(PT::Mc[i * n + j], pa[j], s);
             }
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
@@ -508,7 +513,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], res[i], s);
+          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], res[i], s);
           W[o + a] = s;
         }
       }
@@ -528,7 +533,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int a = 0; a < m; ++a) {
           T s = T(0);
 #pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(tb.S[i * m + a], in[i], s);
+          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
           z[a] = s * tb.inv2[a1 * m + a];
         }
         const int o = a1 * TA + q * m;
@@ -536,7 +541,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], z[a], s);
+          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], z[a], s);
           W2[o + i] = s;
         }
       }
@@ -548,7 +553,6 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const int task = rr * NT + tid;
       const int q = task / m;
       if (task < NB && q < P) {
-        const DevTables<T>& tb = tab_fresh<T>(K);
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W2[a * TA + task];
@@ -556,7 +560,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         for (int i = 0; i < m; ++i) {
           T s = T(0);
 #pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(tb.S[i * m + a], in[a], s);
+          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
           xo[loff[rr] + i * ld1] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
         }
       }
@@ -717,9 +721,11 @@ hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour
   return g.dim == 2 ? dispatch_k<2>(g, prec, mode, colour, b, x, st) : dispatch_k<3>(g, prec, mode, colour, b, x, st);
 }
 
-// Packed launches exist for the two multiplicative kernels (the V-cycle smoothers).
 template <int D, int K>
 static hipError_t group_prec(int prec, int mode, int colour, const ColourPassMember* m, int nm, hipStream_t st) {
+  if (mode == kModeAdditive)
+    return prec == 0 ? launch_group<D, K, double, kModeAdditive>(colour, m, nm, st)
+                     : launch_group<D, K, float, kModeAdditive>(colour, m, nm, st);
   if (mode == kModeMultiplicative)
     return prec == 0 ? launch_group<D, K, double, kModeMultiplicative>(colour, m, nm, st)
                      : launch_group<D, K, float, kModeMultiplicative>(colour, m, nm, st);
