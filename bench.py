@@ -36,15 +36,19 @@ def colour_pass_flops(d, k):
     """Algorithmic flops of one patch: interior-row residual by sum factorisation with reuse,
     FD solve (S^T, eigenvalue scaling, S per direction) and update.  The 1D patch rows have
     nnz = (2k-2)(k+1) + (2k+1) structural nonzeros (a cell-interior node couples to its cell's
-    k+1 nodes, the middle vertex to all 2k+1); products with structural zeros are not counted."""
+    k+1 nodes, the middle vertex to all 2k+1); products with structural zeros are not counted.
+    The eigenvectors are even or odd under the patch mirror, so one application of S or S^T to a
+    line takes (m^2+1)/2 multiply-adds and m-1 additions.  fma = 2 flops, mul/add = 1."""
     n, m = 2 * k + 1, 2 * k - 1
     nnz = (2 * k - 2) * (k + 1) + (2 * k + 1)
+    s_fma, s_add = (m * m + 1) // 2, m - 1
     if d == 3:
-        macs = (2 * nnz * n * n + 3 * nnz * n * m + m * m * (2 * nnz + m + m * m)
-                + m ** 4 + m * m * (2 * m * m + m) + 2 * m ** 4 + m ** 3)
+        fma = 2 * nnz * n * n + 3 * nnz * n * m + 2 * nnz * m * m + m ** 3 + 6 * m * m * s_fma + m ** 3
+        mul, add = m ** 3, 6 * m * m * s_add
     else:
-        macs = 2 * nnz * n + m * (2 * nnz + m + m * m) + m * (2 * m * m + m) + m * m * m + m * m
-    return 2 * macs
+        fma = 2 * nnz * n + 2 * nnz * m + m * m + 4 * m * s_fma + m * m
+        mul, add = m * m, 4 * m * s_add
+    return 2 * fma + mul + add
 
 
 def colour_pass_bytes(d, k, es):

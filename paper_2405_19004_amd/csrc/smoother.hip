@@ -125,6 +125,56 @@ __device__ __forceinline__ const DevTables<T>& tab_fresh(int k) {
   return *reinterpret_cast<const DevTables<T>*>(reinterpret_cast<const char*>(&tab<T>(k)) + z);
 }
 
+// Eigenvector applications with the mirror parity of the patch eigenvectors (the 1D patch pair
+// is symmetric under i -> m-1-i, so S[m-1-i][a] = par[a] S[i][a]): an even vector only sees
+// v_i + v_{m-1-i}, an odd one v_i - v_{m-1-i}, which halves the multiply-adds.
+// t[a] = sum_i S[i][a] v[i]
+template <typename T, int K>
+__device__ __forceinline__ void apply_st(const T (&v)[2 * K - 1], T (&t)[2 * K - 1]) {
+  using PT = gen::PatchTables<T, K>;
+  constexpr int m = 2 * K - 1, h = K - 1;
+  T e[K], o[K];
+#pragma unroll
+  for (int i = 0; i < h; ++i) {
+    e[i] = v[i] + v[m - 1 - i];
+    o[i] = v[i] - v[m - 1 - i];
+  }
+  e[h] = v[h];
+#pragma unroll
+  for (int a = 0; a < m; ++a) {
+    T s = T(0);
+    if (PT::par[a] > 0) {
+#pragma unroll
+      for (int i = 0; i <= h; ++i) s = fma(PT::S[i * m + a], e[i], s);
+    } else {
+#pragma unroll
+      for (int i = 0; i < h; ++i) s = fma(PT::S[i * m + a], o[i], s);
+    }
+    t[a] = s;
+  }
+}
+
+// w[i] = sum_a S[i][a] t[a]: w_i = E_i + O_i and w_{m-1-i} = E_i - O_i with E (O) the even (odd) part
+template <typename T, int K>
+__device__ __forceinline__ void apply_s(const T (&t)[2 * K - 1], T (&w)[2 * K - 1]) {
+  using PT = gen::PatchTables<T, K>;
+  constexpr int m = 2 * K - 1, h = K - 1;
+#pragma unroll
+  for (int i = 0; i <= h; ++i) {
+    T ev = T(0), od = T(0);
+#pragma unroll
+    for (int a = 0; a < m; ++a) {
+      if (PT::par[a] > 0) {
+        ev = fma(PT::S[i * m + a], t[a], ev);
+      } else if (i < h) {
+        od = fma(PT::S[i * m + a], t[a], od);
+      }
+    }
+    w[i] = ev + od;
+    if (i < h) w[m - 1 - i] = ev - od;
+  }
+}
+
 // One workgroup's share of a colour pass: patches of block `blk` of the colour described by
 // (p0, p1, p2, cnt0, cnt1, groups0) on a level with n1d nodes per direction.
 template <int D, int K, typename T, int MODE, int PPW>
@@ -342,13 +392,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           }
         }
         const int o = i1 * SI1 + q * mm + i0;
+        T t[m];
+        apply_st<T, K>(res, t);
 #pragma unroll
-        for (int a = 0; a < m; ++a) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], res[i], s);
-          W4[o + a * m] = s;
-        }
+        for (int a = 0; a < m; ++a) W4[o + a * m] = t[a];
       }
     }
     __syncthreads();
@@ -363,13 +410,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W4[i * SI1 + task];
         const int o = i0 * SI0 + q * mm + a2 * m;
+        T t[m];
+        apply_st<T, K>(in, t);
 #pragma unroll
-        for (int a = 0; a < m; ++a) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
-          W5[o + a] = s;
-        }
+        for (int a = 0; a < m; ++a) W5[o + a] = t[a];
       }
     }
     __syncthreads();
@@ -385,21 +429,14 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W5[i * SI0 + task];
         const int li = (a2 * m + a1) * m;
+        apply_st<T, K>(in, z);
 #pragma unroll
-        for (int a = 0; a < m; ++a) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
-          z[a] = s * tb.inv3[li + a];
-        }
+        for (int a = 0; a < m; ++a) z[a] *= tb.inv3[li + a];
         const int o = a1 * SA1 + q * mm + a2 * m;
+        T w[m];
+        apply_s<T, K>(z, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], z[a], s);
-          W6[o + i] = s;
-        }
+        for (int i = 0; i < m; ++i) W6[o + i] = w[i];
       }
     }
     __syncthreads();
@@ -414,13 +451,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W6[a * SA1 + task];
         const int o = a2 * SA2 + q * mm + i0;
+        T w[m];
+        apply_s<T, K>(in, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
-          W7[o + i * m] = s;
-        }
+        for (int i = 0; i < m; ++i) W7[o + i * m] = w[i];
       }
     }
     __syncthreads();
@@ -433,13 +467,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W7[a * SA2 + task];
+        T w[m];
+        apply_s<T, K>(in, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
-          xo[loff[rr] + i * ld2] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
-        }
+        for (int i = 0; i < m; ++i) xo[loff[rr] + i * ld2] = BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]);
       }
     }
   } else {
@@ -509,13 +540,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           }
         }
         const int o = i0 * T0 + q * m;
+        T t[m];
+        apply_st<T, K>(res, t);
 #pragma unroll
-        for (int a = 0; a < m; ++a) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], res[i], s);
-          W[o + a] = s;
-        }
+        for (int a = 0; a < m; ++a) W[o + a] = t[a];
       }
     }
     __syncthreads();
@@ -529,21 +557,14 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T in[m], z[m];
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W[i * T0 + task];
+        apply_st<T, K>(in, z);
 #pragma unroll
-        for (int a = 0; a < m; ++a) {
-          T s = T(0);
-#pragma unroll
-          for (int i = 0; i < m; ++i) s = fma(PT::S[i * m + a], in[i], s);
-          z[a] = s * tb.inv2[a1 * m + a];
-        }
+        for (int a = 0; a < m; ++a) z[a] *= tb.inv2[a1 * m + a];
         const int o = a1 * TA + q * m;
+        T w[m];
+        apply_s<T, K>(z, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], z[a], s);
-          W2[o + i] = s;
-        }
+        for (int i = 0; i < m; ++i) W2[o + i] = w[i];
       }
     }
     __syncthreads();
@@ -556,13 +577,10 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W2[a * TA + task];
+        T w[m];
+        apply_s<T, K>(in, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int a = 0; a < m; ++a) s = fma(PT::S[i * m + a], in[a], s);
-          xo[loff[rr] + i * ld1] = BND ? sol_scale * s : fma(sol_scale, s, xpre[rr][i]);
-        }
+        for (int i = 0; i < m; ++i) xo[loff[rr] + i * ld1] = BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]);
       }
     }
   }
