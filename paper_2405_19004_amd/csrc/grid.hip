@@ -239,10 +239,13 @@ struct OpStream {
   static constexpr int IX = TX + K + 1, IY = TY + K + 1;  // input extents [o - K, o + T]
 };
 
+// pq_part != null (y = A x only): pq_part[block] = sum over the block's outputs of x_i y_i in FP64,
+// the partial sums of the CG product p.Ap.
 template <int K, typename T, bool RESID>
 __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* __restrict__ x, const T* __restrict__ b,
                                                                      T* __restrict__ y, long long n1d, int tiles0,
-                                                                     int tiles1, int cz, T scale) {
+                                                                     int tiles1, int cz, T scale,
+                                                                     double* __restrict__ pq_part) {
   using S = OpStream<K>;
   constexpr int NT = S::NT, TX = S::TX, TY = S::TY, IX = S::IX, IY = S::IY, CX = S::CX, NP = K + 1;
   constexpr int PL = IY * IX;                  // values of one input plane tile
@@ -357,6 +360,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
   // x2 in cell form: cell g spans node planes gK .. gK+K; zm/zq[0] is its left plane
   T zm[NP], zq[NP];
   T carry = T(0);
+  double pq = 0.0;
   zm[0] = zq[0] = T(0);
   if (g0 > 0) {
     fetch((g0 - 1) * K, 1);
@@ -402,7 +406,9 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
       const long long zg = g * K + li;
       if (col_out && zg >= 1) {
         const long long gi = zg * n1d2 + gy * n1d + gx;
-        y[gi] = RESID ? b[gi] - scale * s : scale * s;
+        const T v = RESID ? b[gi] - scale * s : scale * s;
+        y[gi] = v;
+        if (!RESID && pq_part) pq = fma((double)x[gi], (double)v, pq);
       }
     }
     carry = T(0);
@@ -410,6 +416,17 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
+  }
+  if (!RESID && pq_part) {
+    // fixed-order block reduction (the LDS buffers are free after the last barrier of the loop)
+    __shared__ double red[NT];
+    red[tid] = pq;
+    __syncthreads();
+    for (int w = 1; w < NT; w *= 2) {
+      if (tid % (2 * w) == 0 && tid + w < NT) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) pq_part[blockIdx.x] = red[0];
   }
 }
 
@@ -960,26 +977,36 @@ namespace {
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-template <int K, typename T>
-hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+template <int K>
+long long op_stream_blocks(const LevelGeom& g, int* t0_out, int* cz_out) {
   using S = OpStream<K>;
-  const int t0 = ceil_div(g.ncells, S::CX), t1 = t0;
+  const int t0 = ceil_div(g.ncells, S::CX);
   // enough workgroups to fill the chip, chunks of at least 4 cells along x2
-  const long long tiles = (long long)t0 * t1;
+  const long long tiles = (long long)t0 * t0;
   long long chunks = (2048 + tiles - 1) / tiles;
   if (chunks > g.ncells / 4) chunks = g.ncells / 4;
   if (chunks < 1) chunks = 1;
   const int cz = (int)((g.ncells + chunks - 1) / chunks);
   chunks = (g.ncells + cz - 1) / cz;
-  const long long blocks = tiles * chunks;
+  *t0_out = t0;
+  *cz_out = cz;
+  return tiles * chunks;
+}
+
+template <int K, typename T>
+hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st,
+                            double* pq_part = nullptr) {
+  using S = OpStream<K>;
+  int t0, cz;
+  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const T scale = (T)g.h;  // A_h = h A_1 in 3D
   if (b)
     hipLaunchKernelGGL((op_stream_kernel<K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
-                       (const T*)b, (T*)y, g.n1d, t0, t1, cz, scale);
+                       (const T*)b, (T*)y, g.n1d, t0, t0, cz, scale, (double*)nullptr);
   else
     hipLaunchKernelGGL((op_stream_kernel<K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
-                       (const T*)nullptr, (T*)y, g.n1d, t0, t1, cz, scale);
+                       (const T*)nullptr, (T*)y, g.n1d, t0, t0, cz, scale, pq_part);
   return hipGetLastError();
 }
 
@@ -1115,6 +1142,50 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
 
 hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b, void* y, hipStream_t st) {
   VPS_DISPATCH(op_launch, g, prec, x, b, y, st);
+}
+
+namespace {
+__global__ void sum_parts_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+template <int K>
+hipError_t op_pq_k(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
+                   hipStream_t st, bool* fused) {
+  int t0, cz;
+  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
+  if (blocks > max_parts) return hipSuccess;  // too many partial sums: the caller takes the unfused path
+  hipError_t e = op_stream_launch<K, double>(g, p, nullptr, q, st, part);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)part, (int)blocks, out);
+  *fused = true;
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
+                              hipStream_t st, bool* fused) {
+  *fused = false;
+  if (!(g.dim == 3 && kOpStream3D && g.ncells >= kOpStreamMinCells)) return hipSuccess;
+  switch (g.k) {
+    case 1: return op_pq_k<1>(g, p, q, part, max_parts, out, st, fused);
+    case 2: return op_pq_k<2>(g, p, q, part, max_parts, out, st, fused);
+    case 3: return op_pq_k<3>(g, p, q, part, max_parts, out, st, fused);
+    case 4: return op_pq_k<4>(g, p, q, part, max_parts, out, st, fused);
+    case 5: return op_pq_k<5>(g, p, q, part, max_parts, out, st, fused);
+    case 6: return op_pq_k<6>(g, p, q, part, max_parts, out, st, fused);
+    case 7: return op_pq_k<7>(g, p, q, part, max_parts, out, st, fused);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st) {

@@ -61,6 +61,10 @@ hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour
 
 // grid.hip (interior outputs only)
 hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b_or_null, void* y, hipStream_t st);
+// q = A p in FP64 with out[0] = p.q summed in a fixed order from per-workgroup partials (at most
+// max_parts of them); *fused = false (nothing launched) where that form is not available.
+hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
+                              hipStream_t st, bool* fused);
 // Restriction in separable passes; t1, t2 are scratch of restrict_scratch_elems(fine) elements each.
 hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t1, void* t2,
                            hipStream_t st);

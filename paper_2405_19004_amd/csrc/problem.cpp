@@ -466,8 +466,13 @@ Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) 
 Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
   (void)mode;
   const long long N = p->lv[p->L].N;
-  VPS_HIP(launch_operator(p->geom(p->L), 0, p->p, nullptr, p->q, p->stream));
-  VPS_HIP(launch_dot2(p->p, p->q, nullptr, nullptr, N, p->partial, p->sc + kScPQ, p->stream));
+  bool fused = false;
+  VPS_HIP(launch_operator_pq(p->geom(p->L), p->p, p->q, p->partial, 2 * reduction_parts(), p->sc + kScPQ, p->stream,
+                             &fused));
+  if (!fused) {
+    VPS_HIP(launch_operator(p->geom(p->L), 0, p->p, nullptr, p->q, p->stream));
+    VPS_HIP(launch_dot2(p->p, p->q, nullptr, nullptr, N, p->partial, p->sc + kScPQ, p->stream));
+  }
   float* r32 = mode == 1 ? static_cast<float*>(p->lv[p->L].b[1]) : nullptr;  // input of the FP32 V-cycle
   VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, N, p->sc, p->partial, r32, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));

@@ -96,10 +96,9 @@ __global__ void finalize1_kernel(const double* __restrict__ partial, int nparts,
   block_reduce2(s0, 0.0, &out[0], &dummy);
 }
 
-// CG step: x += alpha p, r -= alpha q, with alpha = s[RZ] / s[PQ];
-// partials of r.r (slot 0) and r.z (slot 1, z = the previous preconditioned residual).
-// With r32 != null the updated residual is also stored rounded to FP32 (the input of the FP32
-// preconditioner), which saves a separate cast pass.
+// CG step: x += alpha p, r -= alpha q, alpha = s[RZ] / s[PQ]; partials of r.r (slot 0) and r.z
+// (slot 1, z = the previous preconditioned residual).  With r32 != null the updated residual is also
+// stored rounded to FP32 (the input of the FP32 preconditioner), which saves a separate cast pass.
 __global__ void cg_update_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
                                  const double* __restrict__ q, const double* __restrict__ z, long long n,
                                  const double* __restrict__ sc, double* __restrict__ partial, float* __restrict__ r32) {
