@@ -25,6 +25,7 @@
 // All kernels here write interior nodes only; boundary entries of outputs are
 // zeroed by zero_boundary_kernel where the caller needs it.
 #include "device_common.hpp"
+#include "patch_tables_gen.hpp"
 #include "kernels.hpp"
 
 namespace vps {
@@ -107,7 +108,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   // stage x0: rows (z, y) of the input block
   const bool xin = o0 - K >= 1 && o0 - K + TI0 - 1 <= n1d - 2;
   for (int task = tid; task < TI2 * TI1; task += NT) {
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
     const int zl = task / TI1, yl = task - zl * TI1;
     const long long gz = D == 3 ? o2 - K + zl : 0, gy = o1 - K + yl;
     T in[TI0];
@@ -121,8 +122,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
       for (int t = 0; t < W; ++t) {
         if (c > 0 && t < K) continue;
-        sm = fma(tb.Mb[c * W + t], in[xo - c + t], sm);
-        sa = fma(tb.Ab[c * W + t], in[xo - c + t], sa);
+        sm = fma(CT::Mb[c * W + t], in[xo - c + t], sm);
+        sa = fma(CT::Ab[c * W + t], in[xo - c + t], sa);
       }
       PM[(zl * TI1 + yl) * TO0 + xo] = sm;
       PA[(zl * TI1 + yl) * TO0 + xo] = sa;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
   if constexpr (D == 2) {
     // stage x1: columns xo, outputs y = A1 (M1 x) + M1 (A1 x)
     for (int task = tid; task < TO0; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int xo = task;
       T pm[TI1], pa[TI1];
 #pragma unroll
@@ -149,8 +150,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          s = fma(tb.Ab[c * W + t], pm[yo - c + t], s);
-          s = fma(tb.Mb[c * W + t], pa[yo - c + t], s);
+          s = fma(CT::Ab[c * W + t], pm[yo - c + t], s);
+          s = fma(CT::Mb[c * W + t], pa[yo - c + t], s);
         }
         const long long gy = o1 + yo;
         if (!is_bnd(gx, n1d) && !is_bnd(gy, n1d)) {
@@ -164,7 +165,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
     __shared__ T V[TI2 * TO1 * TO0];
     // stage x1: columns (z, xo)
     for (int task = tid; task < TI2 * TO0; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int zl = task / TO0, xo = task - zl * TO0;
       T pm[TI1], pa[TI1];
 #pragma unroll
@@ -179,9 +180,9 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          su = fma(tb.Mb[c * W + t], pm[yo - c + t], su);
-          sv = fma(tb.Ab[c * W + t], pm[yo - c + t], sv);
-          sv = fma(tb.Mb[c * W + t], pa[yo - c + t], sv);
+          su = fma(CT::Mb[c * W + t], pm[yo - c + t], su);
+          sv = fma(CT::Ab[c * W + t], pm[yo - c + t], sv);
+          sv = fma(CT::Mb[c * W + t], pa[yo - c + t], sv);
         }
         U[(zl * TO1 + yo) * TO0 + xo] = su;
         V[(zl * TO1 + yo) * TO0 + xo] = sv;
@@ -190,7 +191,7 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
     __syncthreads();
     // stage x2: columns (yo, xo); y = A1 U + M1 V
     for (int task = tid; task < TO1 * TO0; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int yo = task / TO0, xo = task - yo * TO0;
       T u[TI2], v[TI2];
 #pragma unroll
@@ -207,8 +208,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          s = fma(tb.Ab[c * W + t], u[zo - c + t], s);
-          s = fma(tb.Mb[c * W + t], v[zo - c + t], s);
+          s = fma(CT::Ab[c * W + t], u[zo - c + t], s);
+          s = fma(CT::Mb[c * W + t], v[zo - c + t], s);
         }
         const long long gz = o2 + zo;
         if (col_ok && !is_bnd(gz, n1d)) {
@@ -297,7 +298,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
   auto reduce = [&](int nb) {
     __syncthreads();
     for (int task = tid; task < nb * IY * CX; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int j = task / (IY * CX), rem = task - j * (IY * CX);
       const int r = rem / CX, cx = rem - r * CX;
       T in[2 * K + 1];
@@ -309,14 +310,14 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
         if (li == 0) {
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
-            sm = fma(tb.Mh[K * NP + q], in[q], sm);
-            sa = fma(tb.Ah[K * NP + q], in[q], sa);
+            sm = fma(CT::Mh[K * NP + q], in[q], sm);
+            sa = fma(CT::Ah[K * NP + q], in[q], sa);
           }
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          sm = fma(tb.Mh[li * NP + q], in[K + q], sm);
-          sa = fma(tb.Ah[li * NP + q], in[K + q], sa);
+          sm = fma(CT::Mh[li * NP + q], in[K + q], sm);
+          sa = fma(CT::Ah[li * NP + q], in[K + q], sa);
         }
         Rm[(j * IY + r) * TX + cx * K + li] = sm;
         Ra[(j * IY + r) * TX + cx * K + li] = sa;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     }
     __syncthreads();
     for (int task = tid; task < nb * TX * CX; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int j = task / (TX * CX), rem = task - j * (TX * CX);
       const int cy = rem / TX, c = rem - cy * TX;
       T im[2 * K + 1], ia[2 * K + 1];
@@ -339,16 +340,16 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
         if (li == 0) {
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
-            su = fma(tb.Mh[K * NP + q], im[q], su);
-            sv = fma(tb.Ah[K * NP + q], im[q], sv);
-            sv = fma(tb.Mh[K * NP + q], ia[q], sv);
+            su = fma(CT::Mh[K * NP + q], im[q], su);
+            sv = fma(CT::Ah[K * NP + q], im[q], sv);
+            sv = fma(CT::Mh[K * NP + q], ia[q], sv);
           }
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          su = fma(tb.Mh[li * NP + q], im[K + q], su);
-          sv = fma(tb.Ah[li * NP + q], im[K + q], sv);
-          sv = fma(tb.Mh[li * NP + q], ia[K + q], sv);
+          su = fma(CT::Mh[li * NP + q], im[K + q], su);
+          sv = fma(CT::Ah[li * NP + q], im[K + q], sv);
+          sv = fma(CT::Mh[li * NP + q], ia[K + q], sv);
         }
         Pm[(j * TY + cy * K + li) * TX + c] = su;
         Pq[(j * TY + cy * K + li) * TX + c] = sv;
@@ -379,9 +380,9 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
       zq[1 + j] = Pq[j * TY * TX + tid];
     }
     __syncthreads();
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
+    for (int j = 0; j < NP; ++j) carry = fma(CT::Ah[K * NP + j], zm[j], fma(CT::Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
   } else {
@@ -397,12 +398,12 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
       zq[1 + j] = Pq[j * TY * TX + tid];
     }
     __syncthreads();
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
 #pragma unroll
     for (int li = 0; li < K; ++li) {
       T s = li == 0 ? carry : T(0);
 #pragma unroll
-      for (int j = 0; j < NP; ++j) s = fma(tb.Ah[li * NP + j], zm[j], fma(tb.Mh[li * NP + j], zq[j], s));
+      for (int j = 0; j < NP; ++j) s = fma(CT::Ah[li * NP + j], zm[j], fma(CT::Mh[li * NP + j], zq[j], s));
       const long long zg = g * K + li;
       if (col_out && zg >= 1) {
         const long long gi = zg * n1d2 + gy * n1d + gx;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     }
     carry = T(0);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) carry = fma(tb.Ah[K * NP + j], zm[j], fma(tb.Mh[K * NP + j], zq[j], carry));
+    for (int j = 0; j < NP; ++j) carry = fma(CT::Ah[K * NP + j], zm[j], fma(CT::Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
   }
@@ -456,7 +457,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   __shared__ T T1[TIz * TI * TO];
   // stage x0: coarse rows
   for (int task = tid; task < TIz * TI; task += NT) {
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
     const int zl = task / TI, yl = task - zl * TI;
     const long long gz = D == 3 ? c2 + zl : 0, gy = c1 + yl;
     const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && (D == 2 || (gz < n1dc && !is_bnd(gz, n1dc)));
@@ -473,7 +474,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
       for (int a = 0; a < NP; ++a) {
         if (q == 0 && a > 0) continue;
-        s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+        s = fma(CT::P[q * NP + a], in[K * cc + a], s);
       }
       T1[(zl * TI + yl) * TO + xo] = s;
     }
@@ -481,7 +482,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   __syncthreads();
   if constexpr (D == 2) {
     for (int task = tid; task < TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int xo = task;
       T in[TI];
 #pragma unroll
@@ -494,7 +495,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gy = f1 + yo;
         if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] += s;
@@ -503,7 +504,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   } else {
     __shared__ T T2[TI * TO * TO];
     for (int task = tid; task < TI * TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int zl = task / TO, xo = task - zl * TO;
       T in[TI];
 #pragma unroll
@@ -515,14 +516,14 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
         }
         T2[(zl * TO + yo) * TO + xo] = s;
       }
     }
     __syncthreads();
     for (int task = tid; task < TO * TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int yo = task / TO, xo = task - yo * TO;
       T in[TI];
 #pragma unroll
@@ -536,7 +537,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(tb.P[q * NP + a], in[K * cc + a], s);
+          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gz = f2 + zo;
         if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] += s;
@@ -568,7 +569,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
   __shared__ T T1[TIz * TI * TO];
   for (int task = tid; task < TIz * TI; task += NT) {
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
     const int zl = task / TI, yl = task - zl * TI;
     const long long gz = D == 3 ? f2 + zl : 0, gy = f1 + yl;
     const bool ok = !is_bnd(gy, n1df) && (D == 2 || !is_bnd(gz, n1df));
@@ -583,7 +584,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
 #pragma unroll
       for (int t = 0; t < RW; ++t) {
         if (a > 0 && t < 2 * K) continue;
-        s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+        s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
       }
       T1[(zl * TI + yl) * TO + xo] = s;
     }
@@ -591,7 +592,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   __syncthreads();
   if constexpr (D == 2) {
     for (int task = tid; task < TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int xo = task;
       T in[TI];
 #pragma unroll
@@ -604,7 +605,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
 #pragma unroll
         for (int t = 0; t < RW; ++t) {
           if (a > 0 && t < 2 * K) continue;
-          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
         }
         const long long gy = c1 + yo;
         if (!is_bnd(gx, n1dc) && !is_bnd(gy, n1dc)) rc[gy * n1dc + gx] = s;
@@ -613,7 +614,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
   } else {
     __shared__ T T2[TI * TO * TO];
     for (int task = tid; task < TI * TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int zl = task / TO, xo = task - zl * TO;
       T in[TI];
 #pragma unroll
@@ -625,14 +626,14 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
 #pragma unroll
         for (int t = 0; t < RW; ++t) {
           if (a > 0 && t < 2 * K) continue;
-          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
         }
         T2[(zl * TO + yo) * TO + xo] = s;
       }
     }
     __syncthreads();
     for (int task = tid; task < TO * TO; task += NT) {
-      const DevTables<T>& tb = gtab_fresh<T>(K);
+      using CT = gen::CellTables<T, K>;
       const int yo = task / TO, xo = task - yo * TO;
       T in[TI];
 #pragma unroll
@@ -646,7 +647,7 @@ __global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(con
 #pragma unroll
         for (int t = 0; t < RW; ++t) {
           if (a > 0 && t < 2 * K) continue;
-          s = fma(tb.Rb[a * RW + t], in[2 * K * cc + t], s);
+          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
         }
         const long long gz = c2 + zo;
         if (ok && !is_bnd(gz, n1dc)) rc[gz * nc2 + gy * n1dc + gx] = s;
@@ -673,7 +674,7 @@ __global__ void restrict_pass_kernel(const T* __restrict__ in, T* __restrict__ o
   const int i1 = t / o0, i0 = t - i1 * o0;
   const long long ie0 = AXIS == 0 ? nf : o0, ie1 = AXIS == 1 ? nf : o1;
   const long long stride = AXIS == 0 ? 1 : AXIS == 1 ? ie0 : ie0 * ie1;
-  const DevTables<T>& tb = gtab<T>(K);
+  using CT = gen::CellTables<T, K>;
   for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
     const long long oidx = ((long long)i2 * o1 + i1) * o0 + i0;
     const int J = AXIS == 0 ? i0 : AXIS == 1 ? i1 : i2;
@@ -694,13 +695,13 @@ __global__ void restrict_pass_kernel(const T* __restrict__ in, T* __restrict__ o
         const int f = f0 + tt;
         const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
         const T v = p[fc * stride];
-        s = fma(tb.Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
+        s = fma(CT::Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
       }
     } else {
 #pragma unroll
       for (int tt = 2 * K; tt < RW; ++tt) {
         const int f = f0 + tt;  // in [1, nf - 2] for a cell-interior coarse node
-        s = fma(tb.Rb[a * RW + tt], p[f * stride], s);
+        s = fma(CT::Rb[a * RW + tt], p[f * stride], s);
       }
     }
     out[oidx] = s;
@@ -718,7 +719,7 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
   const int t = blockIdx.x * blockDim.x + threadIdx.x;  // (i1, C)
   if (t >= (ncc + 1) * o1) return;
   const int i1 = t / (ncc + 1), C = t - i1 * (ncc + 1);
-  const DevTables<T>& tb = gtab<T>(K);
+  using CT = gen::CellTables<T, K>;
   for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
     const bool row_zero = i1 == 0 || i1 == nf - 1 || (o2 > 1 && (i2 == 0 || i2 == nf - 1));
     const long long row = (long long)i2 * o1 + i1;
@@ -741,7 +742,7 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
     for (int a = 0; a < K; ++a) {
       T s = T(0);
 #pragma unroll
-      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma(tb.Rb[a * RW + tt], w[tt], s);
+      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma(CT::Rb[a * RW + tt], w[tt], s);
       q[K * C + a] = (row_zero || (a == 0 && C == 0)) ? T(0) : s;
     }
   }
@@ -770,15 +771,16 @@ struct ResPlane {
 
 // in[t] = fine nodes 2K(C-1) + t, t < 4K (the runs of cells C-1 and C): coarse node a of cell C
 template <int K, typename T>
-__device__ __forceinline__ T restrict_run(const DevTables<T>& tb, const T* in, int a) {
+__device__ __forceinline__ T restrict_run(const T* in, int a) {
+  using CT = gen::CellTables<T, K>;
   constexpr int NP = K + 1, RUN = 2 * K;
   T s = T(0);
   if (a == 0) {
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + K], in[q], s);
+    for (int q = 0; q < RUN; ++q) s = fma(CT::P[q * NP + K], in[q], s);
   }
 #pragma unroll
-  for (int q = 0; q < RUN; ++q) s = fma(tb.P[q * NP + a], in[RUN + q], s);
+  for (int q = 0; q < RUN; ++q) s = fma(CT::P[q * NP + a], in[RUN + q], s);
   return s;
 }
 
@@ -803,18 +805,18 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   }
   __syncthreads();
   for (int task = tid; task < IX * CX; task += NT) {
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
     const int r = task / CX, cx = task - r * CX;
     T in[2 * RUN];
 #pragma unroll
     for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * IX + RUN * cx + t];
 #pragma unroll
-    for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = restrict_run<K, T>(tb, in, a);
+    for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = restrict_run<K, T>(in, a);
   }
   __syncthreads();
   T* out = tz + zf * nc * nc;
   for (int task = tid; task < TX * CX; task += NT) {
-    const DevTables<T>& tb = gtab_fresh<T>(K);
+    using CT = gen::CellTables<T, K>;
     const int cy = task / TX, c = task - cy * TX;
     T in[2 * RUN];
 #pragma unroll
@@ -823,7 +825,7 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
 #pragma unroll
     for (int a = 0; a < K; ++a) {
       const long long gy = o1 + cy * K + a;
-      if (gx < nc && gy < nc) out[gy * nc + gx] = restrict_run<K, T>(tb, in, a);
+      if (gx < nc && gy < nc) out[gy * nc + gx] = restrict_run<K, T>(in, a);
     }
   }
 }
@@ -841,7 +843,7 @@ __global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ t
     rc[t] = T(0);
     return;
   }
-  const DevTables<T>& tb = gtab<T>(K);
+  using CT = gen::CellTables<T, K>;
   const long long C = zc / K;
   const int a = (int)(zc - C * K);
   const T* col = tz + rem;
@@ -850,13 +852,13 @@ __global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ t
 #pragma unroll
     for (int q = 0; q < RUN; ++q) {
       const long long zf = RUN * (C - 1) + q;  // >= 0 since zc > 0 means C >= 1 here
-      if (zf >= 1) s = fma(tb.P[q * NP + K], col[zf * nc2], s);
+      if (zf >= 1) s = fma(CT::P[q * NP + K], col[zf * nc2], s);
     }
   }
 #pragma unroll
   for (int q = 0; q < RUN; ++q) {
     const long long zf = RUN * C + q;
-    if (zf >= 1 && zf <= nf - 2) s = fma(tb.P[q * NP + a], col[zf * nc2], s);
+    if (zf >= 1 && zf <= nf - 2) s = fma(CT::P[q * NP + a], col[zf * nc2], s);
   }
   rc[t] = s;
 }
