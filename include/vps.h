@@ -68,6 +68,9 @@ enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
                                          beta in both modes).  Default: descending (symmetric V-cycle). */
 #define VPS_FLAG_BOUNDARY_SMOOTHER 0x10u /* V-cycles smooth with the "Boundary" kernel
                                             (VPS_MULTIPLICATIVE_BOUNDARY below; Sec. 4.1.3) */
+#define VPS_FLAG_GRAPHS 0x20u /* replay the CG preconditioner from a HIP graph captured on first use
+                                 instead of launching its kernels one by one (same results; measured
+                                 slower than direct launches for these solves, so off by default) */
 
 typedef struct vps_problem vps_problem;
 

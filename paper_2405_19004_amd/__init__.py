@@ -19,7 +19,7 @@ VPS_FP64, VPS_FP32 = 0, 1
 VPS_MULTIPLICATIVE, VPS_ADDITIVE, VPS_MULTIPLICATIVE_BOUNDARY = 0, 1, 2
 VPS_SOLVE_FP64, VPS_SOLVE_MIXED = 0, 1
 VPS_FLAG_FP64_HIERARCHY, VPS_FLAG_FP32_HIERARCHY, VPS_FLAG_NO_SOLVER, VPS_FLAG_POST_SAME_ORDER = 0x1, 0x2, 0x4, 0x8
-VPS_FLAG_BOUNDARY_SMOOTHER = 0x10
+VPS_FLAG_BOUNDARY_SMOOTHER, VPS_FLAG_GRAPHS = 0x10, 0x20
 
 _STATUS_NAMES = {0: "VPS_OK", -1: "VPS_EINVAL", -2: "VPS_ENOMEM", -3: "VPS_EHIP", -4: "VPS_ENOCONV",
                  -5: "VPS_EBREAKDOWN", -6: "VPS_ENOTFINITE", -7: "VPS_EBUSY"}

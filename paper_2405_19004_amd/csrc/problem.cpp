@@ -99,6 +99,12 @@ size_t footprint_bytes(int dim, int degree, int L, unsigned flags) {
 
 Problem::~Problem() {
   if (stream) hipStreamSynchronize(stream);
+  if (graph_stream) (void)hipStreamSynchronize(graph_stream);
+  for (hipGraphExec_t g : precond_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (graph_in) (void)hipEventDestroy(graph_in);
+  if (graph_out) (void)hipEventDestroy(graph_out);
+  if (graph_stream) (void)hipStreamDestroy(graph_stream);
   for (void* a : allocs) hipFree(a);
   if (host_sc) hipHostFree(host_sc);
   if (host_bad) hipHostFree(host_bad);
@@ -121,6 +127,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   p->stream = st;
   p->post_same_order = flags & 0x8u;
   p->boundary_smoother = flags & 0x10u;
+  p->use_graphs = flags & 0x20u;
   p->lv.resize(L + 1);
   Plan pl = plan(dim, k, L, flags);
   std::vector<void*> ptrs;
@@ -385,10 +392,12 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
 
 // ------------------------------------------------------------------------ CG
 
+namespace {
+
 // z = M r with the problem's CG vectors, and sc[RZNew] = r.z.  Mixed mode: the FP32 copy of r
 // must already be in the level-L FP32 rhs (cg_update or pcg_begin writes it); the widening of
 // the FP32 result is fused with the dot product.
-Status precondition(Problem* p, int mode) {
+Status precondition_launch(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
   if (mode == 0) {
     VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
@@ -400,6 +409,53 @@ Status precondition(Problem* p, int mode) {
   VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
   VPS_TRY(vcycle_top(p, 1, p->L, B.b[1], B.x[1], true));
   VPS_HIP(launch_widen_dot((const float*)B.x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew, p->stream));
+  return Status::ok();
+}
+
+}  // namespace
+
+// With VPS_FLAG_GRAPHS the preconditioner (~20 kernels per level, fixed arguments) is captured once
+// per solve mode into a HIP graph (fills are kernels, there are no memset nodes) and replayed;
+// where capture is not possible the kernels are launched directly.
+Status precondition(Problem* p, int mode) {
+  if (!p->use_graphs || p->graph_failed[mode]) return precondition_launch(p, mode);
+  if (!p->graph_stream) {
+    if (hipStreamCreateWithFlags(&p->graph_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->graph_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->graph_out, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      p->use_graphs = false;
+      return precondition_launch(p, mode);
+    }
+  }
+  if (!p->precond_graph[mode]) {
+    // capture on the private stream: every launch of precondition_launch goes to p->stream
+    hipStream_t caller = p->stream;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(p->graph_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      p->graph_failed[mode] = true;
+      return precondition_launch(p, mode);
+    }
+    p->stream = p->graph_stream;
+    const Status s = precondition_launch(p, mode);
+    p->stream = caller;
+    hipError_t e = hipStreamEndCapture(p->graph_stream, &g);
+    if (s.code == 0 && e == hipSuccess && g) e = hipGraphInstantiate(&p->precond_graph[mode], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (s.code) return s;
+    if (e != hipSuccess || !p->precond_graph[mode]) {
+      (void)hipGetLastError();
+      p->precond_graph[mode] = nullptr;
+      p->graph_failed[mode] = true;
+      return precondition_launch(p, mode);
+    }
+  }
+  VPS_HIP(hipEventRecord(p->graph_in, p->stream));
+  VPS_HIP(hipStreamWaitEvent(p->graph_stream, p->graph_in, 0));
+  VPS_HIP(hipGraphLaunch(p->precond_graph[mode], p->graph_stream));
+  VPS_HIP(hipEventRecord(p->graph_out, p->graph_stream));
+  VPS_HIP(hipStreamWaitEvent(p->stream, p->graph_out, 0));
   return Status::ok();
 }
 

@@ -44,6 +44,14 @@ struct Problem {
   size_t bytes = 0;
   bool post_same_order = false;
   bool boundary_smoother = false;  // V-cycles smooth with the Boundary colour-pass kernel
+  // CG preconditioner per solve mode, captured once as a HIP graph and replayed every iteration
+  // (the caller's stream may be the null stream, which cannot be captured: the graph is captured
+  // on and replayed from a private stream ordered against the caller's by events)
+  bool use_graphs = false;
+  hipGraphExec_t precond_graph[2] = {nullptr, nullptr};
+  bool graph_failed[2] = {false, false};
+  hipStream_t graph_stream = nullptr;
+  hipEvent_t graph_in = nullptr, graph_out = nullptr;
 
   ~Problem();
   bool has(int prec) const;
