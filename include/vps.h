@@ -56,7 +56,12 @@ enum vps_status {
 };
 
 enum vps_prec { VPS_FP64 = 0, VPS_FP32 = 1 };
-enum vps_smooth { VPS_MULTIPLICATIVE = 0, VPS_ADDITIVE = 1, VPS_MULTIPLICATIVE_BOUNDARY = 2 };
+enum vps_smooth {
+  VPS_MULTIPLICATIVE = 0,
+  VPS_ADDITIVE = 1,
+  VPS_MULTIPLICATIVE_BOUNDARY = 2,
+  VPS_MULTIPLICATIVE_SEPARATE = 3
+};
 enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
 
 /* vps_create flags */
@@ -68,6 +73,8 @@ enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
                                          beta in both modes).  Default: descending (symmetric V-cycle). */
 #define VPS_FLAG_BOUNDARY_SMOOTHER 0x10u /* V-cycles smooth with the "Boundary" kernel
                                             (VPS_MULTIPLICATIVE_BOUNDARY below; Sec. 4.1.3) */
+#define VPS_FLAG_SEPARATE_SMOOTHER 0x40u /* V-cycles smooth in the "Separate" form
+                                            (VPS_MULTIPLICATIVE_SEPARATE below; Sec. 4.1, Table 6) */
 #define VPS_FLAG_GRAPHS 0x20u /* replay the CG preconditioner from a HIP graph captured on first use
                                  instead of launching its kernels one by one (same results; measured
                                  slower than direct launches for these solves, so off by default) */
@@ -129,7 +136,11 @@ int vps_residual(vps_problem* p, int level, int prec, const void* b, const void*
  *   beyond rounding).
  * VPS_MULTIPLICATIVE_BOUNDARY: the multiplicative smoother computed as in Sec. 4.1.3
  *   (eq:A_ib_2d/3d): since A_j^{-1} is exact, x_j^I <- A_j^{-1}(b_j^I - A^{IB} x_j^B); the old
- *   interior values are never read.  Equal to VPS_MULTIPLICATIVE up to rounding. */
+ *   interior values are never read.  Equal to VPS_MULTIPLICATIVE up to rounding.
+ * VPS_MULTIPLICATIVE_SEPARATE: the multiplicative smoother as two kernels per colour (the
+ *   "Separate" kernels of Sec. 4.1, Table 6): the residual b - A x by the operator kernel into
+ *   the level's residual buffer, then x^I += A_j^{-1} r^I.  Needs the hierarchy flag of `prec`.
+ *   Equal to VPS_MULTIPLICATIVE up to rounding. */
 int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int reverse_colors, const void* b, void* x);
 
 /* One colour of Alg. 3 (mode as above) on `level`; color in 0..2^dim-1 where the colour of the

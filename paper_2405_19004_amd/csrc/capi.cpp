@@ -204,7 +204,8 @@ int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int revers
   return guarded([&]() -> int {
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
-    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY)
+    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY &&
+        mode != VPS_MULTIPLICATIVE_SEPARATE)
       return fail(VPS_EINVAL, "bad smoother mode");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");
     return from(vps::smoother(p->impl, level, prec, mode, reverse_colors != 0, b, x));
@@ -215,7 +216,8 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
   return guarded([&]() -> int {
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
-    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY)
+    if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY &&
+        mode != VPS_MULTIPLICATIVE_SEPARATE)
       return fail(VPS_EINVAL, "bad smoother mode");
     if (color < 0 || color >= (1 << p->impl->dim)) return fail(VPS_EINVAL, "color out of range");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");
@@ -229,8 +231,8 @@ int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, v
     if (int e = check_prec(prec)) return e;
     if (!r_fine || !r_coarse) return fail(VPS_EINVAL, "null vector");
     const vps::LevelBuffers& B = p->impl->lv[fine_level];
-    if (!B.t1[prec]) return fail(VPS_EINVAL, "restriction in this precision needs the matching hierarchy flag");
-    hipError_t e = vps::launch_restrict(p->impl->geom(fine_level), prec, r_fine, r_coarse, B.t1[prec], B.t2[prec],
+    if (!B.t[prec]) return fail(VPS_EINVAL, "restriction in this precision needs the matching hierarchy flag");
+    hipError_t e = vps::launch_restrict(p->impl->geom(fine_level), prec, r_fine, r_coarse, B.t[prec],
                                         p->impl->stream);
     return e == hipSuccess ? VPS_OK : fail(VPS_EHIP, std::string("restrict launch: ") + hipGetErrorString(e));
   });

@@ -1061,45 +1061,29 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
   return hipGetLastError();
 }
 
-#ifdef VPS_RES_PASSES_3D
-constexpr bool kResPlane3D = false;  // three separable passes in 3D as well (comparison builds)
-#else
-constexpr bool kResPlane3D = true;
-#endif
-
+// 3D: in-plane reduction of every fine plane, then the x2 reduction (scratch t: nf x nc x nc).
+// 2D: x0 pass into t (nf x nc), then the x1 pass.
 template <int D, int K, typename T>
-hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t1, void* t2) {
+hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t) {
   const int nf = (int)fine.n1d, nc = (int)(K * (fine.ncells / 2) + 1);
   const int ncc = (nc - 1) / K;
-  // grid x: 256-thread blocks over one output plane (rows flattened); grid y: planes
-  auto g = [](long long plane, int planes) {
-    return dim3((unsigned)((plane + 255) / 256), (unsigned)(planes < 65535 ? planes : 65535));
-  };
-  if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
-    return hipErrorInvalidConfiguration;
-  if (D == 3 && kResPlane3D) {
+  if (D == 3) {
     using S = ResPlane<K>;
     const int tiles = ceil_div(nc, S::TX);
     if ((long long)tiles * tiles > 0x7fffffffLL || nf - 2 > 65535) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)(nf - 2)), dim3(S::NT),
-                       0, st, (const T*)rf, (T*)t1, (long long)nf, (long long)nc, tiles);
+                       0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
     const long long ntot = (long long)nc * nc * nc;
     hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
-                       (const T*)t1, (T*)rc, (long long)nf, (long long)nc);
-  } else if (D == 2) {
-    // x0: [nf][nf] -> T1 [nf][nc]; x1: T1 -> rc [nc][nc]
-    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, 1), dim3(256), 0, st, (const T*)rf,
-                       (T*)t1, nf, nc, nf, 1);
-    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), g((long long)nc * nc, 1), dim3(256), 0, st, (const T*)t1,
-                       (T*)rc, nf, nc, nc, nc, 1);
+                       (const T*)t, (T*)rc, (long long)nf, (long long)nc);
   } else {
-    // x0: [nf][nf][nf] -> T1 [nf][nf][nc]; x1: T1 -> T2 [nf][nc][nc]; x2: T2 -> rc [nc][nc][nc]
-    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), g((long long)(ncc + 1) * nf, nf), dim3(256), 0, st, (const T*)rf,
-                       (T*)t1, nf, nc, nf, nf);
-    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), g((long long)nc * nc, nf), dim3(256), 0, st, (const T*)t1,
-                       (T*)t2, nf, nc, nc, nc, nf);
-    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 2>), g((long long)nc * nc, nc), dim3(256), 0, st, (const T*)t2,
-                       (T*)rc, nf, nc, nc, nc, nc);
+    // grid x: 256-thread blocks over one output plane (rows flattened)
+    if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
+      return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), dim3((unsigned)(((long long)(ncc + 1) * nf + 255) / 256)), dim3(256),
+                       0, st, (const T*)rf, (T*)t, nf, nc, nf, 1);
+    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), dim3((unsigned)(((long long)nc * nc + 255) / 256)), dim3(256),
+                       0, st, (const T*)t, (T*)rc, nf, nc, nc, nc, 1);
   }
   return hipGetLastError();
 }
@@ -1194,9 +1178,8 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
   VPS_DISPATCH(pro_launch, fine, prec, e, xf, st);
 }
 
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t1, void* t2,
-                           hipStream_t st) {
-  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t1, t2);
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st) {
+  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t);
 }
 
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st) {

@@ -65,12 +65,12 @@ hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const vo
 // max_parts of them); *fused = false (nothing launched) where that form is not available.
 hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
                               hipStream_t st, bool* fused);
-// Restriction in separable passes; t1, t2 are scratch of restrict_scratch_elems(fine) elements each.
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t1, void* t2,
-                           hipStream_t st);
+// Restriction P^T of a fine-level vector (fine boundary entries ignored, coarse boundary written 0);
+// t is scratch of restrict_scratch_elems(fine) elements.
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st);
 inline long long restrict_scratch_elems(int dim, int k, int fine_level) {
   const long long nf = (long long)k * (1LL << fine_level) + 1, nc = (long long)k * (1LL << (fine_level - 1)) + 1;
-  return dim == 2 ? nf * nc : nf * nf * nc;
+  return dim == 2 ? nf * nc : nf * nc * nc;
 }
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st);
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);

@@ -23,7 +23,12 @@
 namespace vps {
 
 // Kernel mode of the V-cycle smoothing steps.
-inline int vcycle_mode(const Problem* p) { return p->boundary_smoother ? kModeBoundary : kModeMultiplicative; }
+// Smoother mode of the Separate form (not a kernel mode): per colour, the global residual by the
+// operator kernel, then the local solves of the additive kernel on that residual.
+constexpr int kSmoothSeparate = 3;
+inline int vcycle_mode(const Problem* p) {
+  return p->separate_smoother ? kSmoothSeparate : p->boundary_smoother ? kModeBoundary : kModeMultiplicative;
+}
 
 long long level_nodes(int dim, int k, int level) {
   long long n = (long long)k * (1LL << level) + 1;
@@ -63,12 +68,8 @@ Plan plan(int dim, int k, int L, unsigned flags) {
         pl.sizes.push_back(N * es);  // b
         pl.sizes.push_back(N * es);  // x
       }
-      if (lvl >= 2) {
-        pl.sizes.push_back(N * es);  // r
-        const size_t T = (size_t)restrict_scratch_elems(dim, k, lvl) * es;
-        pl.sizes.push_back(T);  // restriction scratch t1
-        pl.sizes.push_back(T);  // t2
-      }
+      pl.sizes.push_back(N * es);  // r (V-cycle residual; the Separate smoother's residual on every level)
+      if (lvl >= 2) pl.sizes.push_back((size_t)restrict_scratch_elems(dim, k, lvl) * es);  // restriction scratch
     }
   }
   if (h32) {
@@ -127,6 +128,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   p->stream = st;
   p->post_same_order = flags & 0x8u;
   p->boundary_smoother = flags & 0x10u;
+  p->separate_smoother = flags & 0x40u;
   p->use_graphs = flags & 0x20u;
   p->lv.resize(L + 1);
   Plan pl = plan(dim, k, L, flags);
@@ -162,11 +164,8 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
         B.b[prec] = p->allocs[idx++];
         B.x[prec] = p->allocs[idx++];
       }
-      if (lvl >= 2) {
-        B.r[prec] = p->allocs[idx++];
-        B.t1[prec] = p->allocs[idx++];
-        B.t2[prec] = p->allocs[idx++];
-      }
+      B.r[prec] = p->allocs[idx++];
+      if (lvl >= 2) B.t[prec] = p->allocs[idx++];
     }
   }
   if (h32) {
@@ -196,6 +195,15 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
 // ------------------------------------------------------------------ smoothing
 
 Status colour_pass(Problem* p, int level, int prec, int mode, int colour, const void* b, void* x) {
+  if (mode == kSmoothSeparate) {
+    // same-colour patches are disjoint, so one residual r = b - A x (before the colour) serves them
+    // all and x^I += A_j^{-1} r^I is the multiplicative update
+    void* r = p->lv[level].r[prec];
+    if (!r) return Status{-1, "the Separate smoother needs the matching hierarchy flag"};
+    VPS_HIP(launch_operator(p->geom(level), prec, x, b, r, p->stream));
+    VPS_HIP(launch_colour_pass(p->geom(level), prec, kModeAdditive, colour, r, x, p->stream));
+    return Status::ok();
+  }
   VPS_HIP(launch_colour_pass(p->geom(level), prec, mode, colour, b, x, p->stream));
   return Status::ok();
 }
@@ -239,8 +247,8 @@ Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT, bool 
     if (lvl < top) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
     VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), false, b, x, lvl < top || top_zero));
     VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
-    VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
-                            p->lv[lvl].t2[prec], p->stream));
+    VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t[prec],
+                            p->stream));
   }
   VPS_TRY(coarse_solve(p, prec, p->lv[1].b[prec], p->lv[1].x[prec]));
   // ascend
@@ -346,7 +354,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
   for (int i = 0; i < n; ++i) {
     if (!ps[i]->has(prec)) return Status{-1, "V-cycle precision was not requested at creation"};
     if (ps[i]->dim != ps[0]->dim || ps[i]->k != ps[0]->k || ps[i]->stream != ps[0]->stream ||
-        ps[i]->post_same_order != ps[0]->post_same_order || ps[i]->boundary_smoother != ps[0]->boundary_smoother)
+        ps[i]->post_same_order != ps[0]->post_same_order || vcycle_mode(ps[i]) != vcycle_mode(ps[0]))
       return Status{-1, "grouped V-cycle needs one dim, degree, stream, colour order and smoother kernel"};
     Lmax = ps[i]->L > Lmax ? ps[i]->L : Lmax;
   }
@@ -355,7 +363,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
   hipStream_t st = ps[0]->stream;
   auto level_b = [&](int i, int lvl) -> const void* { return lvl == ps[i]->L ? bL[i] : ps[i]->lv[lvl].b[prec]; };
   auto level_x = [&](int i, int lvl) -> void* { return lvl == ps[i]->L ? xL[i] : ps[i]->lv[lvl].x[prec]; };
-  std::vector<ColourPassMember> mem;
+  std::vector<ColourPassMember> mem, sep;
   // x_zero: every member's x is 0 on entry (the first colour then needs no residual, as in smoother())
   auto smooth = [&](int lvl, bool reverse, bool x_zero) -> Status {
     mem.clear();
@@ -363,7 +371,19 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
       if (ps[i]->L >= lvl) mem.push_back({ps[i]->geom(lvl), level_b(i, lvl), level_x(i, lvl)});
     for (int j = 0; j < nc; ++j) {
       const int c = reverse ? nc - 1 - j : j;
-      const int mode = (j == 0 && x_zero) ? kModeAdditive : vcycle_mode(ps[0]);
+      int mode = (j == 0 && x_zero) ? kModeAdditive : vcycle_mode(ps[0]);
+      if (mode == kSmoothSeparate) {
+        // residual of every member, then the packed local solves on it
+        sep.assign(mem.begin(), mem.end());
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+          if (ps[i]->L < lvl) continue;
+          VPS_HIP(launch_operator(ps[i]->geom(lvl), prec, level_x(i, lvl), level_b(i, lvl), ps[i]->lv[lvl].r[prec], st));
+          sep[m++].b = ps[i]->lv[lvl].r[prec];
+        }
+        VPS_HIP(launch_colour_pass_group(dim, k, prec, kModeAdditive, c, sep.data(), (int)sep.size(), st));
+        continue;
+      }
       VPS_HIP(launch_colour_pass_group(dim, k, prec, mode, c, mem.data(), (int)mem.size(), st));
     }
     return Status::ok();
@@ -376,8 +396,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
       if (ps[i]->L < lvl) continue;
       Problem* p = ps[i];
       VPS_HIP(launch_operator(p->geom(lvl), prec, level_x(i, lvl), level_b(i, lvl), p->lv[lvl].r[prec], st));
-      VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t1[prec],
-                              p->lv[lvl].t2[prec], st));
+      VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t[prec], st));
     }
   }
   for (int i = 0; i < n; ++i) VPS_TRY(coarse_solve(ps[i], prec, level_b(i, 1), level_x(i, 1)));

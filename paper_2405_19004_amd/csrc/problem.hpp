@@ -21,9 +21,8 @@ struct LevelBuffers {
   long long N = 0;                  // nodes on the level
   void* b[2] = {nullptr, nullptr};  // V-cycle right-hand side per precision (levels < L; FP32 also L)
   void* x[2] = {nullptr, nullptr};  // V-cycle iterate per precision
-  void* r[2] = {nullptr, nullptr};  // residual per precision (levels >= 2)
-  void* t1[2] = {nullptr, nullptr}; // restriction scratch per precision (levels >= 2)
-  void* t2[2] = {nullptr, nullptr};
+  void* r[2] = {nullptr, nullptr};  // residual per precision (every level)
+  void* t[2] = {nullptr, nullptr};  // restriction scratch per precision (levels >= 2)
 };
 
 struct Problem {
@@ -44,6 +43,7 @@ struct Problem {
   size_t bytes = 0;
   bool post_same_order = false;
   bool boundary_smoother = false;  // V-cycles smooth with the Boundary colour-pass kernel
+  bool separate_smoother = false;  // V-cycles smooth in the Separate form (residual kernel + solve kernel)
   // CG preconditioner per solve mode, captured once as a HIP graph and replayed every iteration
   // (the caller's stream may be the null stream, which cannot be captured: the graph is captured
   // on and replayed from a private stream ordered against the caller's by events)
