@@ -30,6 +30,7 @@ D, K, L = 3, 4, 6
 RTOL = 1e-8
 PEAK_FP32 = 157.3e12  # MI355X published FP32 vector peak
 PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12  # MI355X HBM3E
 
 
 def colour_pass_flops(d, k):
@@ -212,6 +213,33 @@ def fmg_run(v, torch, P, kap, co):
     return res
 
 
+def variants_run(v, torch, P, b, stream):
+    """Colour-pass forms on the finest level (Table 6 analogue): the fused kernel, the Boundary
+    kernel (Sec. 4.1.3) and the Separate pair (residual kernel, then the local-solve kernel), per
+    colour pass averaged over the 8 colours, and the V-cycle with each form."""
+    res = {}
+    flags = v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY | v.VPS_FLAG_POST_SAME_ORDER
+    for name, dt_ in (("fp32", torch.float32), ("fp64", torch.float64)):
+        bb = b.to(dt_)
+        xx = torch.zeros_like(bb)
+        r = torch.empty_like(bb)
+        row = {}
+        for form, mode in (("fused", v.VPS_MULTIPLICATIVE), ("boundary", v.VPS_MULTIPLICATIVE_BOUNDARY),
+                           ("separate", v.VPS_MULTIPLICATIVE_SEPARATE)):
+            row[form + "_colour_pass_us"] = 1e6 * event_time(lambda: [P.color_pass(bb, xx, c, mode) for c in range(8)],
+                                                             stream, 5) / 8
+        row["separate_residual_kernel_us"] = 1e6 * event_time(lambda: P.residual(bb, xx, r), stream, 20)
+        row["separate_solve_kernel_us"] = 1e6 * event_time(lambda: [P.color_pass(r, xx, c, v.VPS_ADDITIVE)
+                                                                    for c in range(8)], stream, 5) / 8
+        for form, fl in (("boundary", v.VPS_FLAG_BOUNDARY_SMOOTHER), ("separate", v.VPS_FLAG_SEPARATE_SMOOTHER)):
+            Q = v.Problem(P.dim, P.degree, P.L, flags | fl | v.VPS_FLAG_NO_SOLVER)
+            row[form + "_vcycle_ms"] = 1e3 * event_time(lambda: Q.vcycle(bb, xx), stream, 5)
+            Q.close()
+        row["fused_vcycle_ms"] = 1e3 * event_time(lambda: P.vcycle(bb, xx), stream, 5)
+        res[name] = {k_: round(v_, 2) for k_, v_ in row.items()}
+    return res
+
+
 def cpu_baseline(N, vcycles_per_solve):
     """The FP64 oracle (NumPy/SciPy) on a bounded sample of the same workload.
 
@@ -339,6 +367,7 @@ def main():
         per[name] = {"smoothing_step_ms": 1e3 * t_s, "smoother_dof_per_s": N / t_s,
                      "vcycle_ms": 1e3 * t_v, "vcycle_dof_per_s": N / t_v}
     out["smoother_vcycle"] = per
+    out["smoother_variants"] = variants_run(v, torch, P, b, stream)
     out["fmg"] = fmg_run(v, torch, P, kap, co)
 
     # roofline of the dominant kernel: the FP32 colour pass on the finest level
@@ -356,16 +385,29 @@ def main():
         rec = json.load(open(tf))
         if rec.get("source_hash") == smoother_source_hash():  # counters describe this exact kernel source
             traffic = rec.get("bytes_per_launch")
-    out["roofline"] = {"bound": "alu", "achieved": flops / t_all / 1e12, "peak": PEAK_FP32 / 1e12,
-                       "unit": "TFLOP/s", "frac": flops / t_all / PEAK_FP32, "traffic": traffic,
-                       "kernel": "colour_pass_kernel<3,4,float,multiplicative,2 patches per workgroup>", "avg_launch_us": 1e6 * t_all,
-                       "algorithmic_bytes_per_launch": bytes_, "algorithmic_gbps": bytes_ / t_all / 1e9,
-                       "flops_per_launch": flops, "launches_timed": launches}
+    # the binding roof is the one with the longer time at peak: HBM (algorithmic bytes / 8 TB/s) or
+    # the vector ALU (algorithmic flops / 157.3 TFLOP/s)
+    t_hbm, t_alu = bytes_ / PEAK_HBM, flops / PEAK_FP32
+    common = {"kernel": "colour_pass_kernel<3,4,float,multiplicative,2 patches per workgroup>",
+              "avg_launch_us": 1e6 * t_all, "algorithmic_bytes_per_launch": bytes_, "flops_per_launch": flops,
+              "launches_timed": launches, "traffic": traffic,
+              "alu": {"achieved_tflops": flops / t_all / 1e12, "peak_tflops": PEAK_FP32 / 1e12,
+                      "frac": flops / t_all / PEAK_FP32},
+              "hbm": {"achieved_gbps": bytes_ / t_all / 1e9, "peak_gbps": PEAK_HBM / 1e9,
+                      "frac": bytes_ / t_all / PEAK_HBM}}
+    if t_hbm >= t_alu:
+        out["roofline"] = dict(bound="hbm", achieved=bytes_ / t_all / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                               frac=bytes_ / t_all / PEAK_HBM, **common)
+    else:
+        out["roofline"] = dict(bound="alu", achieved=flops / t_all / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                               frac=flops / t_all / PEAK_FP32, **common)
     xz = torch.zeros_like(b)
     t64 = event_time(lambda: [P.color_pass(b, xz, c) for c in range(8)], stream, 5) / 8
-    out["roofline_fp64_colour_pass"] = {"achieved": flops / t64 / 1e12, "peak": PEAK_FP64 / 1e12,
-                                        "frac": flops / t64 / PEAK_FP64, "avg_launch_us": 1e6 * t64,
-                                        "algorithmic_gbps": colour_pass_bytes(D, K, 8) * patches / t64 / 1e9}
+    bytes64 = colour_pass_bytes(D, K, 8) * patches
+    out["roofline_fp64_colour_pass"] = {"bound": "hbm" if bytes64 / PEAK_HBM >= flops / PEAK_FP64 else "alu",
+                                        "avg_launch_us": 1e6 * t64,
+                                        "hbm_gbps": bytes64 / t64 / 1e9, "hbm_frac": bytes64 / t64 / PEAK_HBM,
+                                        "alu_tflops": flops / t64 / 1e12, "alu_frac": flops / t64 / PEAK_FP64}
     P.close()
 
     if a.serve > 0:

@@ -1,0 +1,56 @@
+"""bench.py on the CPU: the single-GPU guard and the structural facts its flop model relies on."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import smoother
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+def test_patch_rows_have_the_counted_nonzeros(k):
+    """The model counts nnz = (2k-2)(k+1) + 2k+1 nonzeros in the interior rows of the 1D patch
+    matrices (a cell-interior node couples to its own cell only)."""
+    A, M = smoother.patch_1d_matrices(k, 1.0)
+    nnz = (2 * k - 2) * (k + 1) + (2 * k + 1)
+    for B in (A, M):
+        rows = B[1:-1, :]
+        assert np.count_nonzero(np.abs(rows) > 1e-14 * np.abs(rows).max()) == nnz
+
+
+@pytest.mark.parametrize("k", range(1, 8))
+def test_patch_eigenvectors_are_even_or_odd(k):
+    """S and S^T cost (m^2+1)/2 multiply-adds per line: the k even and k-1 odd eigenvectors of the
+    mirror-symmetric interior pair."""
+    A, M = smoother.patch_1d_matrices(k, 1.0)
+    Ai, Mi = A[1:-1, 1:-1], M[1:-1, 1:-1]
+    lam, S = sla.eigh(Ai, Mi)
+    m = 2 * k - 1
+    even = odd = 0
+    for a in range(m):
+        v = S[:, a]
+        if np.allclose(v, v[::-1], atol=1e-10):
+            even += 1
+        elif np.allclose(v, -v[::-1], atol=1e-10):
+            odd += 1
+    assert (even, odd) == (k, k - 1)
+    h = k - 1
+    assert even * (h + 1) + odd * h == (m * m + 1) // 2
+
+
+def test_flop_model_at_degree_4():
+    assert bench.colour_pass_flops(3, 4) == 53201
+    assert bench.colour_pass_bytes(3, 4, 4) == 4 * (9 ** 3 + 2 * 7 ** 3)
