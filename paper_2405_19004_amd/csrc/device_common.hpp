@@ -11,34 +11,19 @@ namespace vps {
 constexpr int kMaxN = 2 * kMaxDegree + 1;  // patch closure points per direction
 constexpr int kMaxM = 2 * kMaxDegree - 1;  // patch interior points per direction
 
-// 1D tables of one degree, reference cell size 1 (see tables.hpp for meanings).
+// Reciprocal eigenvalue sums of one degree (patch pair, reference cell size 1).  The colour pass
+// indexes them by lane, so they live in constant memory; every other 1D table is a compile-time
+// constant (generated header patch_tables_gen.hpp).
 template <typename T>
 struct DevTables {
-  T Mc[kMaxM * kMaxN];  // patch mass, interior rows x closure cols (m x n)
-  T Ac[kMaxM * kMaxN];  // patch stiffness, same shape
-  T S[kMaxM * kMaxM];   // eigenvectors, S[i*m + a]
-  T lam[kMaxM];         // eigenvalues
-  T Mb[kMaxDegree * kMaxN];  // assembled-mass band rows, k x (2k+1)
-  T Ab[kMaxDegree * kMaxN];  // assembled-stiffness band rows
-  T P[kMaxN * (kMaxDegree + 1)];          // prolongation (2k+1) x (k+1)
-  T Rb[kMaxDegree * (4 * kMaxDegree + 1)];  // restriction band rows k x (4k+1)
   T inv3[kMaxM * kMaxM * kMaxM];  // 1 / (lam[a2] + lam[a1] + lam[a0]), index (a2*m + a1)*m + a0
   T inv2[kMaxM * kMaxM];          // 1 / (lam[a1] + lam[a0]),           index a1*m + a0
-  T Ah[(kMaxDegree + 1) * (kMaxDegree + 1)];  // reference cell stiffness (k+1) x (k+1)
-  T Mh[(kMaxDegree + 1) * (kMaxDegree + 1)];  // reference cell mass
 };
 
 template <typename T>
 inline void fill_dev_tables(int k, DevTables<T>& out) {
   const Tables1D& t = tables_for_degree(k);
-  const int n = 2 * k + 1, m = 2 * k - 1, np = k + 1;
-  for (int i = 0; i < m * n; ++i) { out.Mc[i] = (T)t.Mc[i]; out.Ac[i] = (T)t.Ac[i]; }
-  for (int i = 0; i < m * m; ++i) out.S[i] = (T)t.S[i];
-  for (int i = 0; i < m; ++i) out.lam[i] = (T)t.lam[i];
-  for (int i = 0; i < k * n; ++i) { out.Mb[i] = (T)t.Mband[i]; out.Ab[i] = (T)t.Aband[i]; }
-  for (int i = 0; i < n * np; ++i) out.P[i] = (T)t.P[i];
-  for (int i = 0; i < k * (4 * k + 1); ++i) out.Rb[i] = (T)t.Rband[i];
-  for (int i = 0; i < np * np; ++i) { out.Ah[i] = (T)t.Ahat[i]; out.Mh[i] = (T)t.Mhat[i]; }
+  const int m = 2 * k - 1;
   for (int a2 = 0; a2 < m; ++a2)
     for (int a1 = 0; a1 < m; ++a1) {
       out.inv2[a2 * m + a1] = (T)(1.0 / (t.lam[a2] + t.lam[a1]));

@@ -30,26 +30,7 @@
 
 namespace vps {
 
-static __constant__ DevTables<double> g_gtab64[kMaxDegree + 1];
-static __constant__ DevTables<float> g_gtab32[kMaxDegree + 1];
-
-template <typename T>
-__device__ __forceinline__ const DevTables<T>& gtab(int k);
-template <>
-__device__ __forceinline__ const DevTables<double>& gtab<double>(int k) { return g_gtab64[k]; }
-template <>
-__device__ __forceinline__ const DevTables<float>& gtab<float>(int k) { return g_gtab32[k]; }
-
 __device__ __forceinline__ bool is_bnd(long long i, long long n1d) { return i <= 0 || i >= n1d - 1; }
-
-// Tables re-derived through an opaque wave-uniform zero inside each task loop, so
-// the compiler does not hoist every table entry out of the loop into SGPRs (and spill).
-template <typename T>
-__device__ __forceinline__ const DevTables<T>& gtab_fresh(int k) {
-  int z;
-  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-  return *reinterpret_cast<const DevTables<T>*>(reinterpret_cast<const char*>(&gtab<T>(k)) + z);
-}
 
 // Load n values of one row, positions g0 .. g0+n-1, as zero outside the interior (1 .. n1d-2).
 // `interior` (wave-uniform) says the whole range is interior: then the loads are unconditional.
@@ -546,116 +527,6 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   }
 }
 
-// ------------------------------------------------------------- restriction
-
-template <int D, int K>
-struct ResShape {
-  static constexpr int C = K == 1 ? (D == 2 ? 16 : 4) : K == 2 ? (D == 2 ? 8 : 2) : (D == 2 ? 4 : 1);
-  static constexpr int NT = 128;
-};
-
-// r_coarse = P^T r_fine.  Tile: coarse outputs [kC t, kC (t+1)) per axis; fine
-// inputs [2kC t - 2k, 2kC (t+1)].
-template <int D, int K, typename T>
-__global__ __launch_bounds__((ResShape<D, K>::NT)) void restrict_tile_kernel(const T* __restrict__ rf, T* __restrict__ rc,
-                                                                           long long n1dc, long long n1df, int tiles) {
-  constexpr int C = ResShape<D, K>::C, NT = ResShape<D, K>::NT;
-  constexpr int TO = K * C, TI = 2 * K * C + 2 * K + 1, TIz = D == 3 ? TI : 1, RW = 4 * K + 1;
-  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
-  const long long c0 = (long long)tx * TO, c1 = (long long)ty * TO, c2 = (long long)tz * TO;
-  const long long f0 = 2 * c0 - 2 * K, f1 = 2 * c1 - 2 * K, f2 = 2 * c2 - 2 * K;
-  const int tid = threadIdx.x;
-  const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
-  __shared__ T T1[TIz * TI * TO];
-  for (int task = tid; task < TIz * TI; task += NT) {
-    using CT = gen::CellTables<T, K>;
-    const int zl = task / TI, yl = task - zl * TI;
-    const long long gz = D == 3 ? f2 + zl : 0, gy = f1 + yl;
-    const bool ok = !is_bnd(gy, n1df) && (D == 2 || !is_bnd(gz, n1df));
-    T in[TI];
-    const long long gzc = gz < 0 ? 0 : (gz > n1df - 1 ? n1df - 1 : gz), gyc = gy < 0 ? 0 : (gy > n1df - 1 ? n1df - 1 : gy);
-    const bool xin = f0 >= 1 && f0 + TI - 1 <= n1df - 2;
-    load_row<T, TI>(in, rf + (D == 3 ? gzc * nf2 : 0) + gyc * n1df, f0, n1df, xin, ok);
-#pragma unroll
-    for (int xo = 0; xo < TO; ++xo) {
-      const int a = xo % K, cc = xo / K;
-      T s = T(0);
-#pragma unroll
-      for (int t = 0; t < RW; ++t) {
-        if (a > 0 && t < 2 * K) continue;
-        s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
-      }
-      T1[(zl * TI + yl) * TO + xo] = s;
-    }
-  }
-  __syncthreads();
-  if constexpr (D == 2) {
-    for (int task = tid; task < TO; task += NT) {
-      using CT = gen::CellTables<T, K>;
-      const int xo = task;
-      T in[TI];
-#pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T1[j * TO + xo];
-      const long long gx = c0 + xo;
-#pragma unroll
-      for (int yo = 0; yo < TO; ++yo) {
-        const int a = yo % K, cc = yo / K;
-        T s = T(0);
-#pragma unroll
-        for (int t = 0; t < RW; ++t) {
-          if (a > 0 && t < 2 * K) continue;
-          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
-        }
-        const long long gy = c1 + yo;
-        if (!is_bnd(gx, n1dc) && !is_bnd(gy, n1dc)) rc[gy * n1dc + gx] = s;
-      }
-    }
-  } else {
-    __shared__ T T2[TI * TO * TO];
-    for (int task = tid; task < TI * TO; task += NT) {
-      using CT = gen::CellTables<T, K>;
-      const int zl = task / TO, xo = task - zl * TO;
-      T in[TI];
-#pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T1[(zl * TI + j) * TO + xo];
-#pragma unroll
-      for (int yo = 0; yo < TO; ++yo) {
-        const int a = yo % K, cc = yo / K;
-        T s = T(0);
-#pragma unroll
-        for (int t = 0; t < RW; ++t) {
-          if (a > 0 && t < 2 * K) continue;
-          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
-        }
-        T2[(zl * TO + yo) * TO + xo] = s;
-      }
-    }
-    __syncthreads();
-    for (int task = tid; task < TO * TO; task += NT) {
-      using CT = gen::CellTables<T, K>;
-      const int yo = task / TO, xo = task - yo * TO;
-      T in[TI];
-#pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
-      const long long gx = c0 + xo, gy = c1 + yo;
-      const bool ok = !is_bnd(gx, n1dc) && !is_bnd(gy, n1dc);
-#pragma unroll
-      for (int zo = 0; zo < TO; ++zo) {
-        const int a = zo % K, cc = zo / K;
-        T s = T(0);
-#pragma unroll
-        for (int t = 0; t < RW; ++t) {
-          if (a > 0 && t < 2 * K) continue;
-          s = fma(CT::Rb[a * RW + t], in[2 * K * cc + t], s);
-        }
-        const long long gz = c2 + zo;
-        if (ok && !is_bnd(gz, n1dc)) rc[gz * nc2 + gy * n1dc + gx] = s;
-      }
-    }
-  }
-}
-
 // -------------------------------------------------- separable restriction
 
 // One axis of r_coarse = (P1 x P1 x P1)^T r_fine.  `out` has extents (o2, o1, o0); `in` has the
@@ -1027,11 +898,6 @@ hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void
   return hipGetLastError();
 }
 
-#ifdef VPS_OP_TILE_3D
-constexpr bool kOpStream3D = false;  // cubic-tile operator in 3D as well (comparison builds)
-#else
-constexpr bool kOpStream3D = true;
-#endif
 #ifndef VPS_OP_STREAM_MIN_CELLS
 #define VPS_OP_STREAM_MIN_CELLS 64
 #endif
@@ -1039,7 +905,7 @@ constexpr long long kOpStreamMinCells = VPS_OP_STREAM_MIN_CELLS;
 
 template <int D, int K, typename T>
 hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
-  if constexpr (D == 3 && kOpStream3D) {
+  if constexpr (D == 3) {
     // small levels have too few column tiles to hide the plane-to-plane chain of the streaming
     // kernel: the cubic tiles run fully in parallel there
     if (g.ncells >= kOpStreamMinCells) return op_stream_launch<K, T>(g, x, b, y, st);
@@ -1161,7 +1027,7 @@ hipError_t op_pq_k(const LevelGeom& g, const double* p, double* q, double* part,
 hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
                               hipStream_t st, bool* fused) {
   *fused = false;
-  if (!(g.dim == 3 && kOpStream3D && g.ncells >= kOpStreamMinCells)) return hipSuccess;
+  if (!(g.dim == 3 && g.ncells >= kOpStreamMinCells)) return hipSuccess;
   switch (g.k) {
     case 1: return op_pq_k<1>(g, p, q, part, max_parts, out, st, fused);
     case 2: return op_pq_k<2>(g, p, q, part, max_parts, out, st, fused);
@@ -1225,16 +1091,5 @@ hipError_t launch_l2_error(const LevelGeom& g, const double* x, const double* V,
   return hipGetLastError();
 }
 
-hipError_t init_grid_tables() {
-  static DevTables<double> h64[kMaxDegree + 1];
-  static DevTables<float> h32[kMaxDegree + 1];
-  for (int k = 1; k <= kMaxDegree; ++k) {
-    fill_dev_tables(k, h64[k]);
-    fill_dev_tables(k, h32[k]);
-  }
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_gtab64), h64, sizeof(h64));
-  if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(g_gtab32), h32, sizeof(h32));
-}
 
 }  // namespace vps

@@ -53,7 +53,6 @@ struct ColourPassMember {
 // per kMaxGroup members.  Each member's arithmetic is exactly that of launch_colour_pass.
 hipError_t launch_colour_pass_group(int dim, int k, int prec, int mode, int colour,
                                     const ColourPassMember* members, int n_members, hipStream_t st);
-hipError_t init_grid_tables();
 
 // smoother.hip
 hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour, const void* b, void* x,

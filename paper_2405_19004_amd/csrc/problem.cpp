@@ -117,7 +117,6 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   static bool tables_ready = false;
   if (!tables_ready) {
     VPS_HIP(init_smoother_tables());
-    VPS_HIP(init_grid_tables());
     tables_ready = true;
   }
   Problem* p = new Problem();
