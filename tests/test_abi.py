@@ -10,7 +10,7 @@ from oracle import basis, fastdiag, transfer
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2405_19004_amd", "libvps.so")
 
-pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libvps.so not built (run __graft_entry__.build())")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libvps.so not built (run python -m paper_2405_19004_amd.build)")
 
 
 def declared_functions():
