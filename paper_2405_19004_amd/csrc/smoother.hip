@@ -301,6 +301,66 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       T* PM = bufA;  // [j1][q][j2][i0]
       T* PA = bufA + n * SJ1;
       // ---- contract x0 with Mc and Ac: lines (q, j2, j1), j1 fastest
+      if constexpr (BND) {
+        // Boundary form: the closure is zero on patch-interior nodes, so an x0 line with j2 and j1
+        // both interior holds only its two end values.  The 4(n-1) face lines of each patch come
+        // first and take the full contraction, the m^2 interior lines a two-term one.
+        constexpr int NF = 4 * (n - 1);
+        // face tasks padded to whole waves, so that no wave mixes the two kinds of line
+        constexpr int FP = (PPW * NF + 63) / 64 * 64, NTASK = FP + PPW * mm;
+        for (int base = 0; base < NTASK; base += NT) {
+          const int task = base + tid;
+          if (task >= NTASK || (task >= PPW * NF && task < FP)) continue;
+          int q, j2, j1;
+          const bool face = task < FP;
+          if (face) {
+            q = task / NF;
+            const int f = task - q * NF;
+            if (f < n) {
+              j2 = 0;
+              j1 = f;
+            } else if (f < 2 * n) {
+              j2 = n - 1;
+              j1 = f - n;
+            } else {
+              j2 = 1 + (f - 2 * n) / 2;
+              j1 = (f & 1) ? n - 1 : 0;  // f - 2n and f have the same parity (2n even)
+            }
+          } else {
+            const int t = task - FP;
+            q = t / mm;
+            const int c = t - q * mm;
+            j2 = 1 + c / m;
+            j1 = 1 + (c - (c / m) * m);
+          }
+          if (q >= P) continue;
+          const int row = (j2 * n + j1) * RS + 2 * K * q;
+          const int o = j1 * SJ1 + (q * n + j2) * m;
+          if (face) {
+            T in[n];
+#pragma unroll
+            for (int j = 0; j < n; ++j) in[j] = X[row + j];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              T sm = T(0), sa = T(0);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                sm = fma(PT::Mc[i * n + j], in[j], sm);
+                sa = fma(PT::Ac[i * n + j], in[j], sa);
+              }
+              PM[o + i] = sm;
+              PA[o + i] = sa;
+            }
+          } else {
+            const T e0 = X[row], e1 = X[row + n - 1];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              PM[o + i] = fma(PT::Mc[i * n], e0, PT::Mc[i * n + n - 1] * e1);
+              PA[o + i] = fma(PT::Ac[i * n], e0, PT::Ac[i * n + n - 1] * e1);
+            }
+          }
+        }
+      } else
       for (int base = 0; base < PPW * n * n; base += NT) {
         const int task = base + tid;
         const int q = task / (n * n), r = task - q * (n * n);
