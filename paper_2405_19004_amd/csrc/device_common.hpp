@@ -31,6 +31,33 @@ inline void fill_dev_tables(int k, DevTables<T>& out) {
     }
 }
 
+// s + c x for a coefficient c that is a compile-time table entry.  IEEE arithmetic does not let the
+// compiler drop fma(0, x, s) (x could be infinite), so a structural zero of a table would still cost
+// a multiply-add; here it costs nothing, and for finite x the result is the same bit for bit.
+// Only use it where c folds to a constant: otherwise the test becomes a select.
+template <typename T>
+__device__ __forceinline__ T fma_tab(T c, T x, T s) {
+  return c == T(0) ? s : fma(c, x, s);
+}
+
+// Global access to p at a per-lane byte offset below 4 GiB, p wave-uniform: the load unit adds the
+// 32-bit offset to the scalar base, so the lane needs no 64-bit address arithmetic.
+// p is pinned in scalar registers: the optimiser would otherwise fold the lane offset into one
+// 64-bit per-lane address and add every other uniform row offset to it lane by lane.
+#define VPS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ld_lane(const T* p, unsigned off) {
+  const VPS_GLOBAL char* g = (const VPS_GLOBAL char*)p;
+  asm volatile("" : "+s"(g));
+  return *(const VPS_GLOBAL T*)(g + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_lane(T* p, unsigned off, T v) {
+  VPS_GLOBAL char* g = (VPS_GLOBAL char*)p;
+  asm volatile("" : "+s"(g));
+  *(VPS_GLOBAL T*)(g + off) = v;
+}
+
 // Geometry of one level as the kernels see it.
 struct LevelGeom {
   int dim, k, level;

@@ -103,8 +103,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
       for (int t = 0; t < W; ++t) {
         if (c > 0 && t < K) continue;
-        sm = fma(CT::Mb[c * W + t], in[xo - c + t], sm);
-        sa = fma(CT::Ab[c * W + t], in[xo - c + t], sa);
+        sm = fma_tab(CT::Mb[c * W + t], in[xo - c + t], sm);
+        sa = fma_tab(CT::Ab[c * W + t], in[xo - c + t], sa);
       }
       PM[(zl * TI1 + yl) * TO0 + xo] = sm;
       PA[(zl * TI1 + yl) * TO0 + xo] = sa;
@@ -131,8 +131,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          s = fma(CT::Ab[c * W + t], pm[yo - c + t], s);
-          s = fma(CT::Mb[c * W + t], pa[yo - c + t], s);
+          s = fma_tab(CT::Ab[c * W + t], pm[yo - c + t], s);
+          s = fma_tab(CT::Mb[c * W + t], pa[yo - c + t], s);
         }
         const long long gy = o1 + yo;
         if (!is_bnd(gx, n1d) && !is_bnd(gy, n1d)) {
@@ -161,9 +161,9 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          su = fma(CT::Mb[c * W + t], pm[yo - c + t], su);
-          sv = fma(CT::Ab[c * W + t], pm[yo - c + t], sv);
-          sv = fma(CT::Mb[c * W + t], pa[yo - c + t], sv);
+          su = fma_tab(CT::Mb[c * W + t], pm[yo - c + t], su);
+          sv = fma_tab(CT::Ab[c * W + t], pm[yo - c + t], sv);
+          sv = fma_tab(CT::Mb[c * W + t], pa[yo - c + t], sv);
         }
         U[(zl * TO1 + yo) * TO0 + xo] = su;
         V[(zl * TO1 + yo) * TO0 + xo] = sv;
@@ -189,8 +189,8 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          s = fma(CT::Ab[c * W + t], u[zo - c + t], s);
-          s = fma(CT::Mb[c * W + t], v[zo - c + t], s);
+          s = fma_tab(CT::Ab[c * W + t], u[zo - c + t], s);
+          s = fma_tab(CT::Mb[c * W + t], v[zo - c + t], s);
         }
         const long long gz = o2 + zo;
         if (col_ok && !is_bnd(gz, n1d)) {
@@ -255,17 +255,32 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
   const long long gx = o0 + px, gy = o1 + py;
   const bool col_out = !is_bnd(gx, n1d) && !is_bnd(gy, n1d) && gx < n1d && gy < n1d;
 
-  // registers <- nb node planes zs .. zs+nb-1 of the tile (Dirichlet and outside nodes 0)
+  // registers <- nb node planes zs .. zs+nb-1 of the tile (Dirichlet and outside nodes 0).
+  // Element i = rr NT + tid of a fetch is node (plane i / PL, row, column) of the tile; its byte
+  // offset from the tile corner of plane zs is the same in every fetch, so it is computed once
+  // (~0u marks a node outside the grid's interior in x0 or x1).  The planes valid in a fetch form
+  // the element range [jlo PL, jhi PL), known to the whole workgroup.
   T pre[RB];
+  unsigned poff[RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const int i = rr * NT + tid;
+    const int j = i / PL, rem = i - j * PL;
+    const int r = rem / IX, c = rem - r * IX;
+    const long long sy = o1 - K + r, sx = o0 - K + c;
+    const bool ok = i < K * PL && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
+    poff[rr] = ok ? (unsigned)(((long long)j * n1d2 + (long long)r * n1d + c) * (long long)sizeof(T)) : ~0u;
+  }
+  const long long corner = (o1 - K) * n1d + (o0 - K);  // negative next to the grid's low faces
   auto fetch = [&](long long zs, int nb) {
+    const int jlo = zs < 1 ? (int)(1 - zs) : 0;
+    const int jhi = (int)(zs + nb <= n1d - 1 ? nb : n1d - 1 - zs);
+    const T* plane = x + (zs * n1d2 + corner);  // only ever offset into the grid
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int i = rr * NT + tid;
-      const int j = i / PL, rem = i - j * PL;
-      const int r = rem / IX, c = rem - r * IX;
-      const long long zg = zs + j, sy = o1 - K + r, sx = o0 - K + c;
-      const bool ok = j < nb && zg >= 1 && zg <= n1d - 2 && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
-      pre[rr] = ok ? x[zg * n1d2 + sy * n1d + sx] : T(0);
+      const bool ok = poff[rr] != ~0u && i >= jlo * PL && i < jhi * PL;
+      pre[rr] = ok ? ld_lane(plane, poff[rr]) : T(0);
     }
   };
   auto stage = [&](int nb) {
@@ -291,14 +306,14 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
         if (li == 0) {
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
-            sm = fma(CT::Mh[K * NP + q], in[q], sm);
-            sa = fma(CT::Ah[K * NP + q], in[q], sa);
+            sm = fma_tab(CT::Mh[K * NP + q], in[q], sm);
+            sa = fma_tab(CT::Ah[K * NP + q], in[q], sa);
           }
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          sm = fma(CT::Mh[li * NP + q], in[K + q], sm);
-          sa = fma(CT::Ah[li * NP + q], in[K + q], sa);
+          sm = fma_tab(CT::Mh[li * NP + q], in[K + q], sm);
+          sa = fma_tab(CT::Ah[li * NP + q], in[K + q], sa);
         }
         Rm[(j * IY + r) * TX + cx * K + li] = sm;
         Ra[(j * IY + r) * TX + cx * K + li] = sa;
@@ -321,16 +336,16 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
         if (li == 0) {
 #pragma unroll
           for (int q = 0; q < NP; ++q) {
-            su = fma(CT::Mh[K * NP + q], im[q], su);
-            sv = fma(CT::Ah[K * NP + q], im[q], sv);
-            sv = fma(CT::Mh[K * NP + q], ia[q], sv);
+            su = fma_tab(CT::Mh[K * NP + q], im[q], su);
+            sv = fma_tab(CT::Ah[K * NP + q], im[q], sv);
+            sv = fma_tab(CT::Mh[K * NP + q], ia[q], sv);
           }
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          su = fma(CT::Mh[li * NP + q], im[K + q], su);
-          sv = fma(CT::Ah[li * NP + q], im[K + q], sv);
-          sv = fma(CT::Mh[li * NP + q], ia[K + q], sv);
+          su = fma_tab(CT::Mh[li * NP + q], im[K + q], su);
+          sv = fma_tab(CT::Ah[li * NP + q], im[K + q], sv);
+          sv = fma_tab(CT::Mh[li * NP + q], ia[K + q], sv);
         }
         Pm[(j * TY + cy * K + li) * TX + c] = su;
         Pq[(j * TY + cy * K + li) * TX + c] = sv;
@@ -363,7 +378,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     __syncthreads();
     using CT = gen::CellTables<T, K>;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) carry = fma(CT::Ah[K * NP + j], zm[j], fma(CT::Mh[K * NP + j], zq[j], carry));
+    for (int j = 0; j < NP; ++j) carry = fma_tab(CT::Ah[K * NP + j], zm[j], fma_tab(CT::Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
   } else {
@@ -384,7 +399,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     for (int li = 0; li < K; ++li) {
       T s = li == 0 ? carry : T(0);
 #pragma unroll
-      for (int j = 0; j < NP; ++j) s = fma(CT::Ah[li * NP + j], zm[j], fma(CT::Mh[li * NP + j], zq[j], s));
+      for (int j = 0; j < NP; ++j) s = fma_tab(CT::Ah[li * NP + j], zm[j], fma_tab(CT::Mh[li * NP + j], zq[j], s));
       const long long zg = g * K + li;
       if (col_out && zg >= 1) {
         const long long gi = zg * n1d2 + gy * n1d + gx;
@@ -395,7 +410,7 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     }
     carry = T(0);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) carry = fma(CT::Ah[K * NP + j], zm[j], fma(CT::Mh[K * NP + j], zq[j], carry));
+    for (int j = 0; j < NP; ++j) carry = fma_tab(CT::Ah[K * NP + j], zm[j], fma_tab(CT::Mh[K * NP + j], zq[j], carry));
     zm[0] = zm[K];
     zq[0] = zq[K];
   }
@@ -455,7 +470,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
       for (int a = 0; a < NP; ++a) {
         if (q == 0 && a > 0) continue;
-        s = fma(CT::P[q * NP + a], in[K * cc + a], s);
+        s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
       }
       T1[(zl * TI + yl) * TO + xo] = s;
     }
@@ -476,7 +491,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
+          s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gy = f1 + yo;
         if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] += s;
@@ -497,7 +512,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
+          s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
         T2[(zl * TO + yo) * TO + xo] = s;
       }
@@ -518,7 +533,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma(CT::P[q * NP + a], in[K * cc + a], s);
+          s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gz = f2 + zo;
         if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] += s;
@@ -566,7 +581,7 @@ __global__ void restrict_pass_kernel(const T* __restrict__ in, T* __restrict__ o
         const int f = f0 + tt;
         const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
         const T v = p[fc * stride];
-        s = fma(CT::Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
+        s = fma_tab(CT::Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
       }
     } else {
 #pragma unroll
@@ -613,7 +628,7 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
     for (int a = 0; a < K; ++a) {
       T s = T(0);
 #pragma unroll
-      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma(CT::Rb[a * RW + tt], w[tt], s);
+      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma_tab(CT::Rb[a * RW + tt], w[tt], s);
       q[K * C + a] = (row_zero || (a == 0 && C == 0)) ? T(0) : s;
     }
   }
@@ -650,6 +665,8 @@ __device__ __forceinline__ T restrict_run(const T* in, int a) {
 #pragma unroll
     for (int q = 0; q < RUN; ++q) s = fma(CT::P[q * NP + K], in[q], s);
   }
+  // plain multiply-adds here: skipping the few zero entries of P breaks up the paired LDS reads of
+  // `in` and made the kernel slower
 #pragma unroll
   for (int q = 0; q < RUN; ++q) s = fma(CT::P[q * NP + a], in[RUN + q], s);
   return s;
@@ -668,11 +685,13 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;
   const T* fz = rf + zf * nf * nf;
   const int tid = threadIdx.x;
+  // 32-bit plane offsets (the launcher checks nf^2 fits)
+  const int nfi = (int)nf, fy0 = (int)(2 * o1) - 2 * K, fx0 = (int)(2 * o0) - 2 * K;
   for (int i = tid; i < IX * IX; i += NT) {
     const int r = i / IX, c = i - r * IX;
-    const long long fy = 2 * o1 - 2 * K + r, fx = 2 * o0 - 2 * K + c;
-    const bool ok = fy >= 1 && fy <= nf - 2 && fx >= 1 && fx <= nf - 2;
-    X[i] = ok ? fz[fy * nf + fx] : T(0);
+    const int fy = fy0 + r, fx = fx0 + c;
+    const bool ok = fy >= 1 && fy <= nfi - 2 && fx >= 1 && fx <= nfi - 2;
+    X[i] = ok ? ld_lane(fz, (unsigned)(fy * nfi + fx) * (unsigned)sizeof(T)) : T(0);
   }
   __syncthreads();
   for (int task = tid; task < IX * CX; task += NT) {
@@ -701,37 +720,33 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   }
 }
 
+// Workgroup = 64 x 4 coarse nodes (x0 fastest) of one coarse plane zc = blockIdx.z; the plane's
+// cell C and node class a are uniform, so are the coefficients and the fine planes read.
 template <int K, typename T>
-__global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, long long nf,
-                                                        long long nc) {
+__global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc) {
   constexpr int NP = K + 1, RUN = 2 * K;
-  const long long nc2 = nc * nc;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc2 * nc) return;
-  const long long zc = t / nc2, rem = t - zc * nc2;
-  const long long gy = rem / nc, gx = rem - gy * nc;
-  if (zc == 0 || zc == nc - 1 || gy == 0 || gy == nc - 1 || gx == 0 || gx == nc - 1) {
-    rc[t] = T(0);
-    return;
-  }
-  using CT = gen::CellTables<T, K>;
-  const long long C = zc / K;
-  const int a = (int)(zc - C * K);
-  const T* col = tz + rem;
+  const int gx = blockIdx.x * 64 + threadIdx.x, gy = blockIdx.y * 4 + threadIdx.y, zc = blockIdx.z;
+  if (gx >= nc || gy >= nc) return;
+  const long long nc2 = (long long)nc * nc;
+  const unsigned off = (unsigned)(gy * nc + gx) * (unsigned)sizeof(T);  // within a plane
   T s = T(0);
-  if (a == 0) {
+  if (zc > 0 && zc < nc - 1 && gy > 0 && gy < nc - 1 && gx > 0 && gx < nc - 1) {
+    using CT = gen::CellTables<T, K>;
+    const int C = zc / K, a = zc - C * K;
+    if (a == 0) {
+#pragma unroll
+      for (int q = 0; q < RUN; ++q) {
+        const int zf = RUN * (C - 1) + q;  // >= 0 since zc > 0 means C >= 1 here
+        if (zf >= 1) s = fma(CT::P[q * NP + K], ld_lane(tz + zf * nc2, off), s);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < RUN; ++q) {
-      const long long zf = RUN * (C - 1) + q;  // >= 0 since zc > 0 means C >= 1 here
-      if (zf >= 1) s = fma(CT::P[q * NP + K], col[zf * nc2], s);
+      const int zf = RUN * C + q;
+      if (zf >= 1 && zf <= nf - 2) s = fma(CT::P[q * NP + a], ld_lane(tz + zf * nc2, off), s);
     }
   }
-#pragma unroll
-  for (int q = 0; q < RUN; ++q) {
-    const long long zf = RUN * C + q;
-    if (zf >= 1 && zf <= nf - 2) s = fma(CT::P[q * NP + a], col[zf * nc2], s);
-  }
-  rc[t] = s;
+  st_lane(rc + zc * nc2, off, s);
 }
 
 // ------------------------------------------------------- boundary and rhs
@@ -866,10 +881,17 @@ long long op_stream_blocks(const LevelGeom& g, int* t0_out, int* cz_out) {
   return tiles * chunks;
 }
 
+// The streaming kernel addresses a cell's K node planes with 32-bit byte offsets.
+template <int K, typename T>
+bool op_stream_fits(const LevelGeom& g) {
+  return (long long)(K + 1) * g.n1d * g.n1d * (long long)sizeof(T) < (1LL << 32);
+}
+
 template <int K, typename T>
 hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st,
                             double* pq_part = nullptr) {
   using S = OpStream<K>;
+  if (!op_stream_fits<K, T>(g)) return hipErrorInvalidConfiguration;
   int t0, cz;
   const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
@@ -908,7 +930,7 @@ hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, 
   if constexpr (D == 3) {
     // small levels have too few column tiles to hide the plane-to-plane chain of the streaming
     // kernel: the cubic tiles run fully in parallel there
-    if (g.ncells >= kOpStreamMinCells) return op_stream_launch<K, T>(g, x, b, y, st);
+    if (g.ncells >= kOpStreamMinCells && op_stream_fits<K, T>(g)) return op_stream_launch<K, T>(g, x, b, y, st);
     return op_tile_launch<D, K, T>(g, x, b, y, st);
   } else {
     return op_tile_launch<D, K, T>(g, x, b, y, st);
@@ -936,12 +958,14 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
   if (D == 3) {
     using S = ResPlane<K>;
     const int tiles = ceil_div(nc, S::TX);
-    if ((long long)tiles * tiles > 0x7fffffffLL || nf - 2 > 65535) return hipErrorInvalidConfiguration;
+    if ((long long)tiles * tiles > 0x7fffffffLL || nf - 2 > 65535 ||
+        (long long)nf * nf * (long long)sizeof(T) >= (1LL << 31))
+      return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)(nf - 2)), dim3(S::NT),
                        0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
-    const long long ntot = (long long)nc * nc * nc;
-    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((ntot + 255) / 256)), dim3(256), 0, st,
-                       (const T*)t, (T*)rc, (long long)nf, (long long)nc);
+    if (nc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32)) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)nc),
+                       dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc);
   } else {
     // grid x: 256-thread blocks over one output plane (rows flattened)
     if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
@@ -1015,7 +1039,8 @@ hipError_t op_pq_k(const LevelGeom& g, const double* p, double* q, double* part,
                    hipStream_t st, bool* fused) {
   int t0, cz;
   const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
-  if (blocks > max_parts) return hipSuccess;  // too many partial sums: the caller takes the unfused path
+  // too many partial sums, or planes beyond 32-bit offsets: the caller takes the unfused path
+  if (blocks > max_parts || !op_stream_fits<K, double>(g)) return hipSuccess;
   hipError_t e = op_stream_launch<K, double>(g, p, nullptr, q, st, part);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)part, (int)blocks, out);

@@ -115,6 +115,14 @@ struct SmootherLds {
 
 __device__ __forceinline__ bool on_boundary(long long i, long long n1d) { return i == 0 || i == n1d - 1; }
 
+// A per-lane LDS offset the optimiser may not take apart.  Without it, base + i * stride inside an
+// unrolled loop is re-associated into a fresh (quarter-rate) 32-bit multiply per element; behind
+// this barrier each element is the base register plus a constant in the instruction's offset field.
+__device__ __forceinline__ int lds_base(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // The constant tables re-derived through an opaque (but wave-uniform) zero
 // offset: keeps the compiler from hoisting every table load out of a stage's
 // task loop, which would pin more values in SGPRs than exist and spill them.
@@ -145,10 +153,10 @@ __device__ __forceinline__ void apply_st(const T (&v)[2 * K - 1], T (&t)[2 * K -
     T s = T(0);
     if (PT::par[a] > 0) {
 #pragma unroll
-      for (int i = 0; i <= h; ++i) s = fma(PT::S[i * m + a], e[i], s);
+      for (int i = 0; i <= h; ++i) s = fma_tab(PT::S[i * m + a], e[i], s);
     } else {
 #pragma unroll
-      for (int i = 0; i < h; ++i) s = fma(PT::S[i * m + a], o[i], s);
+      for (int i = 0; i < h; ++i) s = fma_tab(PT::S[i * m + a], o[i], s);
     }
     t[a] = s;
   }
@@ -165,12 +173,12 @@ __device__ __forceinline__ void apply_s(const T (&t)[2 * K - 1], T (&w)[2 * K - 
 #pragma unroll
     for (int a = 0; a < m; ++a) {
       if (PT::par[a] > 0) {
-        ev = fma(PT::S[i * m + a], t[a], ev);
+        ev = fma_tab(PT::S[i * m + a], t[a], ev);
       } else if (i < h) {
-        od = fma(PT::S[i * m + a], t[a], od);
+        od = fma_tab(PT::S[i * m + a], t[a], od);
       }
     }
-    w[i] = ev + od;
+    w[i] = i < h ? ev + od : ev;  // the middle row has no odd part
     if (i < h) w[m - 1 - i] = ev - od;
   }
 }
@@ -218,7 +226,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
   constexpr int NB = D == 3 ? PPW * mm : PPW * m;
   constexpr int RB = (NB + NT - 1) / NT;
   T bpre[RB][m], xpre[RB][m];
-  int loff[RB], xoff[RB];
+  unsigned loff[RB];  // byte offset of the line's first node from its plane
+  int xoff[RB];
 #pragma unroll
   for (int rr = 0; rr < RB; ++rr) {
     const int task = rr * NT + tid;
@@ -233,15 +242,16 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       i0 = task - q * m;
     }
     q = min(q, P - 1);
-    const int off = (D == 3 ? ld2 + (1 + i1) * ld1 : ld1) + 2 * K * q + 1 + i0;
-    loff[rr] = off;
+    // node (1 + i1, 1 + i0) of the patch's first interior plane, relative to that plane
+    const int off = (D == 3 ? (1 + i1) * ld1 : 0) + 2 * K * q + 1 + i0;
+    loff[rr] = (unsigned)off * (unsigned)sizeof(T);
     xoff[rr] = (D == 3 ? (n + 1 + i1) * RS : RS) + 2 * K * q + 1 + i0;  // node (i=0) in the LDS closure
     const int st = D == 3 ? ld2 : ld1;
 #pragma unroll
-    for (int i = 0; i < m; ++i) bpre[rr][i] = bo[off + i * st];
+    for (int i = 0; i < m; ++i) bpre[rr][i] = ld_lane(bo + st + i * st, loff[rr]);
     if constexpr (ADD) {
 #pragma unroll
-      for (int i = 0; i < m; ++i) xpre[rr][i] = xo[off + i * st];
+      for (int i = 0; i < m; ++i) xpre[rr][i] = ld_lane(xo + st + i * st, loff[rr]);
     }
   }
 
@@ -261,7 +271,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
       const long long gc = s0 + cl;
       bool bad = gc == 0 || gc == n1d - 1;
       if constexpr (D == 3) bad = bad || (j1 == 0 && lo1) || (j1 == n - 1 && hi1);
-      const int base = (D == 3 ? j1 * ld1 : 0) + cl;
+      const unsigned base = ((D == 3 ? j1 * ld1 : 0) + cl) * (unsigned)sizeof(T);
       const int sstride = D == 3 ? ld2 : ld1;
       // column strictly inside a patch (Boundary mode: its nodes 1..n-2 are patch-interior)
       const bool inner = BND && cl % (2 * K) != 0 && (D == 2 || (j1 > 0 && j1 < n - 1));
@@ -269,9 +279,9 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         if (BND && j > 0 && j < n - 1) {
-          v[j] = inner ? T(0) : xo[base + j * sstride];
+          v[j] = inner ? T(0) : ld_lane(xo + j * sstride, base);
         } else {
-          v[j] = xo[base + j * sstride];
+          v[j] = ld_lane(xo + j * sstride, base);
         }
       }
       const bool lo = D == 3 ? lo2 : lo1, hi = D == 3 ? hi2 : hi1;
@@ -334,8 +344,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             j1 = 1 + (c - (c / m) * m);
           }
           if (q >= P) continue;
-          const int row = (j2 * n + j1) * RS + 2 * K * q;
-          const int o = j1 * SJ1 + (q * n + j2) * m;
+          const int row = lds_base((j2 * n + j1) * RS + 2 * K * q);
+          const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
           if (face) {
             T in[n];
 #pragma unroll
@@ -345,8 +355,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
               T sm = T(0), sa = T(0);
 #pragma unroll
               for (int j = 0; j < n; ++j) {
-                sm = fma(PT::Mc[i * n + j], in[j], sm);
-                sa = fma(PT::Ac[i * n + j], in[j], sa);
+                sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
+                sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
               }
               PM[o + i] = sm;
               PA[o + i] = sa;
@@ -355,8 +365,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             const T e0 = X[row], e1 = X[row + n - 1];
 #pragma unroll
             for (int i = 0; i < m; ++i) {
-              PM[o + i] = fma(PT::Mc[i * n], e0, PT::Mc[i * n + n - 1] * e1);
-              PA[o + i] = fma(PT::Ac[i * n], e0, PT::Ac[i * n + n - 1] * e1);
+              PM[o + i] = fma_tab(PT::Mc[i * n], e0, fma_tab(PT::Mc[i * n + n - 1], e1, T(0)));
+              PA[o + i] = fma_tab(PT::Ac[i * n], e0, fma_tab(PT::Ac[i * n + n - 1], e1, T(0)));
             }
           }
         }
@@ -367,21 +377,22 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         const int j2 = r / n, j1 = r - j2 * n;
         if (task < PPW * n * n && q < P) {
           T in[n];
+          const int row = lds_base((j2 * n + j1) * RS + 2 * K * q);
 #pragma unroll
-          for (int j = 0; j < n; ++j) in[j] = X[(j2 * n + j1) * RS + 2 * K * q + j];
-          const int o = j1 * SJ1 + (q * n + j2) * m;
+          for (int j = 0; j < n; ++j) in[j] = X[row + j];
+          const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sm = fma(PT::Mc[i * n + j], in[j], sm);
+            for (int j = 0; j < n; ++j) sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
             PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sa = fma(PT::Ac[i * n + j], in[j], sa);
+            for (int j = 0; j < n; ++j) sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
             PA[o + i] = sa;
           }
         }
@@ -402,15 +413,15 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             pm[j] = PM[j * SJ1 + ri];
             pa[j] = PA[j * SJ1 + ri];
           }
-          const int o = j2 * SJ2 + q * mm + i0;
+          const int o = lds_base(j2 * SJ2 + q * mm + i0);
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T su = T(0), sv = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              su = fma(PT::Mc[i * n + j], pm[j], su);
-              sv = fma(PT::Ac[i * n + j], pm[j], sv);
-              sv = fma(PT::Mc[i * n + j], pa[j], sv);
+              su = fma_tab(PT::Mc[i * n + j], pm[j], su);
+              sv = fma_tab(PT::Ac[i * n + j], pm[j], sv);
+              sv = fma_tab(PT::Mc[i * n + j], pa[j], sv);
             }
             U[o + i * m] = su;
             V[o + i * m] = sv;
@@ -445,13 +456,13 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             T s = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              s = fma(PT::Ac[i * n + j], u[j], s);
-              s = fma(PT::Mc[i * n + j], v[j], s);
+              s = fma_tab(PT::Ac[i * n + j], u[j], s);
+              s = fma_tab(PT::Mc[i * n + j], v[j], s);
             }
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
-        const int o = i1 * SI1 + q * mm + i0;
+        const int o = lds_base(i1 * SI1 + q * mm + i0);
         T t[m];
         apply_st<T, K>(res, t);
 #pragma unroll
@@ -469,7 +480,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T in[m];
 #pragma unroll
         for (int i = 0; i < m; ++i) in[i] = W4[i * SI1 + task];
-        const int o = i0 * SI0 + q * mm + a2 * m;
+        const int o = lds_base(i0 * SI0 + q * mm + a2 * m);
         T t[m];
         apply_st<T, K>(in, t);
 #pragma unroll
@@ -492,7 +503,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         apply_st<T, K>(in, z);
 #pragma unroll
         for (int a = 0; a < m; ++a) z[a] *= tb.inv3[li + a];
-        const int o = a1 * SA1 + q * mm + a2 * m;
+        const int o = lds_base(a1 * SA1 + q * mm + a2 * m);
         T w[m];
         apply_s<T, K>(z, w);
 #pragma unroll
@@ -510,7 +521,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T in[m];
 #pragma unroll
         for (int a = 0; a < m; ++a) in[a] = W6[a * SA1 + task];
-        const int o = a2 * SA2 + q * mm + i0;
+        const int o = lds_base(a2 * SA2 + q * mm + i0);
         T w[m];
         apply_s<T, K>(in, w);
 #pragma unroll
@@ -530,7 +541,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T w[m];
         apply_s<T, K>(in, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) xo[loff[rr] + i * ld2] = BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]);
+        for (int i = 0; i < m; ++i)
+          st_lane(xo + (1 + i) * ld2, loff[rr], BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]));
       }
     }
   } else {
@@ -548,19 +560,19 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
           T in[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) in[j] = X[j1 * RS + 2 * K * q + j];
-          const int o = j1 * T1 + q * m;
+          const int o = lds_base(j1 * T1 + q * m);
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sm = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sm = fma(PT::Mc[i * n + j], in[j], sm);
+            for (int j = 0; j < n; ++j) sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
             PM[o + i] = sm;
           }
 #pragma unroll
           for (int i = 0; i < m; ++i) {
             T sa = T(0);
 #pragma unroll
-            for (int j = 0; j < n; ++j) sa = fma(PT::Ac[i * n + j], in[j], sa);
+            for (int j = 0; j < n; ++j) sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
             PA[o + i] = sa;
           }
         }
@@ -593,13 +605,13 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
             T s = T(0);
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              s = fma(PT::Ac[i * n + j], pm[j], s);
-              s = fma(PT::Mc[i * n + j], pa[j], s);
+              s = fma_tab(PT::Ac[i * n + j], pm[j], s);
+              s = fma_tab(PT::Mc[i * n + j], pa[j], s);
             }
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
-        const int o = i0 * T0 + q * m;
+        const int o = lds_base(i0 * T0 + q * m);
         T t[m];
         apply_st<T, K>(res, t);
 #pragma unroll
@@ -620,7 +632,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         apply_st<T, K>(in, z);
 #pragma unroll
         for (int a = 0; a < m; ++a) z[a] *= tb.inv2[a1 * m + a];
-        const int o = a1 * TA + q * m;
+        const int o = lds_base(a1 * TA + q * m);
         T w[m];
         apply_s<T, K>(z, w);
 #pragma unroll
@@ -640,7 +652,8 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
         T w[m];
         apply_s<T, K>(in, w);
 #pragma unroll
-        for (int i = 0; i < m; ++i) xo[loff[rr] + i * ld1] = BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]);
+        for (int i = 0; i < m; ++i)
+          st_lane(xo + (1 + i) * ld1, loff[rr], BND ? sol_scale * w[i] : fma(sol_scale, w[i], xpre[rr][i]));
       }
     }
   }

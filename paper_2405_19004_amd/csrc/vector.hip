@@ -103,9 +103,10 @@ __global__ void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
                                  const double* __restrict__ q, const double* __restrict__ z, long long n,
                                  const double* __restrict__ sc, double* __restrict__ partial, float* __restrict__ r32) {
   const double alpha = sc[kScRZ] / sc[kScPQ];
+  if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<double*>(sc)[kScAlpha] = alpha;
   double s0 = 0.0, s1 = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    x[i] = fma(alpha, p[i], x[i]);
+    if (x) x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     if (r32) r32[i] = (float)ri;
@@ -126,6 +127,14 @@ __global__ void widen_dot_kernel(const float* __restrict__ z32, double* __restri
     s0 = fma(r[i], zi, s0);
   }
   block_reduce2(s0, 0.0, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
+}
+
+// x += alpha p with the alpha the residual update stored
+__global__ void cg_x_step_kernel(double* __restrict__ x, const double* __restrict__ p, long long n,
+                                 const double* __restrict__ sc) {
+  const double alpha = sc[kScAlpha];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = fma(alpha, p[i], x[i]);
 }
 
 // p = z + beta p, beta from the scalar block
@@ -210,6 +219,11 @@ hipError_t launch_cg_update(double* x, double* r, const double* p, const double*
 
 hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st) {
   hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(1), 0, st, sc, flexible);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_x_step(double* x, const double* p, long long n, const double* sc, hipStream_t st) {
+  hipLaunchKernelGGL(cg_x_step_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, p, n, sc);
   return hipGetLastError();
 }
 
