@@ -41,9 +41,10 @@ __device__ __forceinline__ T fma_tab(T c, T x, T s) {
 }
 
 // Global access to p at a per-lane byte offset below 4 GiB, p wave-uniform: the load unit adds the
-// 32-bit offset to the scalar base, so the lane needs no 64-bit address arithmetic.
-// p is pinned in scalar registers: the optimiser would otherwise fold the lane offset into one
-// 64-bit per-lane address and add every other uniform row offset to it lane by lane.
+// 32-bit offset to the scalar base, so the lane needs no 64-bit address arithmetic.  p is pinned in
+// scalar registers: the optimiser would otherwise fold the lane offset into one 64-bit per-lane
+// address and add every other uniform base to it lane by lane.  (p must be uniform where it is
+// computed: not a value defined inside a loop whose exit differs between lanes.)
 #define VPS_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 __device__ __forceinline__ T ld_lane(const T* p, unsigned off) {
