@@ -20,7 +20,6 @@ enum : int {
   kScBB = 7,     // b.b
   kScTrue = 8,   // true residual norm squared    (written together with kScAux2)
   kScAux2 = 9,
-  kScAlpha = 12,  // alpha of the current CG iteration (written by the residual update)
   kScCount = 16
 };
 
@@ -89,16 +88,17 @@ hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, 
                                      double* out, int* bad, hipStream_t st);
 hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, long long n,
                        double* partial, double* out, hipStream_t st);
-// r -= alpha q with alpha = rz / pq (also stored in sc[kScAlpha]), partials of r.r and r.z, and
-// r32 = (float) r when r32 != null; x += alpha p as well when x != null
-hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
-                            double* sc, double* partial, float* r32, hipStream_t st);
-// x += sc[kScAlpha] p
-hipError_t launch_cg_x_step(double* x, const double* p, long long n, const double* sc, hipStream_t st);
-// z = (double) z32 and out[0] = r.z (deterministic)
-hipError_t launch_widen_dot(const float* z32, double* z, const double* r, long long n, double* partial, double* out,
-                            hipStream_t st);
+// x += alpha p, r -= alpha q with alpha = rz / pq, partials of r.r and r.z, and r32 = (float) r
+// when r32 != null.  z is the previous preconditioned residual: the FP32 z32 (widened exactly)
+// when non-null, else the FP64 z.
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, const float* z32,
+                            long long n, double* sc, double* partial, float* r32, hipStream_t st);
+// out[0] = r.z32 with z32 widened exactly (deterministic)
+hipError_t launch_dot_rz32(const float* z32, const double* r, long long n, double* partial, double* out,
+                           hipStream_t st);
 hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st);
-hipError_t launch_cg_direction(double* p, const double* z, long long n, const double* sc, hipStream_t st);
+// p = z + beta p (z32 widened exactly when non-null, else z)
+hipError_t launch_cg_direction(double* p, const double* z, const float* z32, long long n, const double* sc,
+                               hipStream_t st);
 
 }  // namespace vps

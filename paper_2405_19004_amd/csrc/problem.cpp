@@ -412,9 +412,15 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
 
 namespace {
 
+// The preconditioned residual of a mixed solve: the FP32 V-cycle's result on the finest level (it
+// stays there until the next preconditioner application); null in FP64 mode, where z is p->z.
+const float* cg_z32(const Problem* p, int mode) {
+  return mode == 1 ? static_cast<const float*>(p->lv[p->L].x[1]) : nullptr;
+}
+
 // z = M r with the problem's CG vectors, and sc[RZNew] = r.z.  Mixed mode: the FP32 copy of r
-// must already be in the level-L FP32 rhs (cg_update or pcg_begin writes it); the widening of
-// the FP32 result is fused with the dot product.
+// must already be in the level-L FP32 rhs (cg_update or pcg_begin writes it), and z stays the FP32
+// result in the level-L FP32 iterate (cg_z32): its consumers widen it exactly as they read it.
 Status precondition_launch(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
   if (mode == 0) {
@@ -426,7 +432,7 @@ Status precondition_launch(Problem* p, int mode) {
   LevelBuffers& B = p->lv[p->L];
   VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
   VPS_TRY(vcycle_top(p, 1, p->L, B.b[1], B.x[1], true));
-  VPS_HIP(launch_widen_dot((const float*)B.x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew, p->stream));
+  VPS_HIP(launch_dot_rz32((const float*)B.x[1], p->r, N, p->partial, p->sc + kScRZNew, p->stream));
   return Status::ok();
 }
 
@@ -502,7 +508,7 @@ Status precondition_group(Problem* const* ps, int n, int mode) {
     if (mode == 0)
       VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
     else
-      VPS_HIP(launch_widen_dot((const float*)p->lv[p->L].x[1], p->z, p->r, N, p->partial, p->sc + kScRZNew,
+      VPS_HIP(launch_dot_rz32((const float*)p->lv[p->L].x[1], p->r, N, p->partial, p->sc + kScRZNew,
                                p->stream));
   }
   return Status::ok();
@@ -533,7 +539,10 @@ Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) 
   if (mode == 1) VPS_HIP(launch_cast(0, p->r, p->lv[p->L].b[1], N, p->stream));
   VPS_TRY(precondition(p, mode));
   VPS_HIP(launch_cg_beta(p->sc, 0, p->stream));  // rz <- rz_new (beta unused here)
-  VPS_HIP(hipMemcpyAsync(p->p, p->z, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  if (mode == 1)
+    VPS_HIP(launch_cast(1, cg_z32(p, mode), p->p, N, p->stream));  // p = z, widened exactly
+  else
+    VPS_HIP(hipMemcpyAsync(p->p, p->z, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   return Status::ok();
 }
 
@@ -548,7 +557,7 @@ Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
     VPS_HIP(launch_dot2(p->p, p->q, nullptr, nullptr, N, p->partial, p->sc + kScPQ, p->stream));
   }
   float* r32 = mode == 1 ? static_cast<float*>(p->lv[p->L].b[1]) : nullptr;  // input of the FP32 V-cycle
-  VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, N, p->sc, p->partial, r32, p->stream));
+  VPS_HIP(launch_cg_update(x, p->r, p->p, p->q, p->z, cg_z32(p, mode), N, p->sc, p->partial, r32, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   (void)cs;
   return Status::ok();
@@ -581,7 +590,7 @@ Status pcg_after_precond(Problem* p, int mode) {
   // flexible (Polak-Ribiere) beta whenever the preconditioner is not symmetric: FP32 V-cycle
   // (rounding) or the literal colour order after the coarse correction
   VPS_HIP(launch_cg_beta(p->sc, (mode == 1 || p->post_same_order) ? 1 : 0, p->stream));
-  VPS_HIP(launch_cg_direction(p->p, p->z, N, p->sc, p->stream));
+  VPS_HIP(launch_cg_direction(p->p, p->z, cg_z32(p, mode), N, p->sc, p->stream));
   return Status::ok();
 }
 

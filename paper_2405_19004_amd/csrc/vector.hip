@@ -96,53 +96,45 @@ __global__ void finalize1_kernel(const double* __restrict__ partial, int nparts,
   block_reduce2(s0, 0.0, &out[0], &dummy);
 }
 
-// CG step: x += alpha p, r -= alpha q, alpha = s[RZ] / s[PQ]; partials of r.r (slot 0) and r.z
-// (slot 1, z = the previous preconditioned residual).  With r32 != null the updated residual is also
-// stored rounded to FP32 (the input of the FP32 preconditioner), which saves a separate cast pass.
+// CG step: x += alpha p, r -= alpha q, alpha = s[RZ] / s[PQ]; partials
+// of r.r (slot 0) and r.z (slot 1, z = the previous preconditioned residual, FP64 or the FP32
+// output of the FP32 preconditioner, widened exactly).  With r32 != null the updated residual is
+// also stored rounded to FP32 (the input of the FP32 preconditioner), which saves a separate cast
+// pass.
+template <typename Z>
 __global__ void cg_update_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                                 const double* __restrict__ q, const double* __restrict__ z, long long n,
+                                 const double* __restrict__ q, const Z* __restrict__ z, long long n,
                                  const double* __restrict__ sc, double* __restrict__ partial, float* __restrict__ r32) {
   const double alpha = sc[kScRZ] / sc[kScPQ];
-  if (blockIdx.x == 0 && threadIdx.x == 0) const_cast<double*>(sc)[kScAlpha] = alpha;
   double s0 = 0.0, s1 = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    if (x) x[i] = fma(alpha, p[i], x[i]);
+    x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     if (r32) r32[i] = (float)ri;
     s0 = fma(ri, ri, s0);
-    s1 = fma(ri, z[i], s1);
+    s1 = fma(ri, (double)z[i], s1);
   }
   block_reduce2(s0, s1, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
 }
 
-// z = (double) z32 and partials of r.z: the widening of the FP32 preconditioner output fused
-// with the dot product CG takes next.
-__global__ void widen_dot_kernel(const float* __restrict__ z32, double* __restrict__ z, const double* __restrict__ r,
-                                 long long n, double* __restrict__ partial) {
+// partials of r.z for the FP32 preconditioner output z32 (widened exactly): the FP64 copy of z is
+// never stored, its consumers widen z32 as they read it.
+__global__ void dot_rz32_kernel(const float* __restrict__ z32, const double* __restrict__ r, long long n,
+                                double* __restrict__ partial) {
   double s0 = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const double zi = (double)z32[i];
-    z[i] = zi;
-    s0 = fma(r[i], zi, s0);
-  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    s0 = fma(r[i], (double)z32[i], s0);
   block_reduce2(s0, 0.0, &partial[2 * blockIdx.x], &partial[2 * blockIdx.x + 1]);
 }
 
-// x += alpha p with the alpha the residual update stored
-__global__ void cg_x_step_kernel(double* __restrict__ x, const double* __restrict__ p, long long n,
-                                 const double* __restrict__ sc) {
-  const double alpha = sc[kScAlpha];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    x[i] = fma(alpha, p[i], x[i]);
-}
-
-// p = z + beta p, beta from the scalar block
-__global__ void cg_direction_kernel(double* __restrict__ p, const double* __restrict__ z, long long n,
+// p = z + beta p, beta from the scalar block (z FP64, or FP32 widened exactly)
+template <typename Z>
+__global__ void cg_direction_kernel(double* __restrict__ p, const Z* __restrict__ z, long long n,
                                     const double* __restrict__ sc) {
   const double beta = sc[kScBeta];
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = fma(beta, p[i], z[i]);
+    p[i] = fma(beta, p[i], (double)z[i]);
 }
 
 // beta = (rz_new - flexible * r_new.z_old) / rz ; rz <- rz_new.  Also flags non-finite values.
@@ -201,18 +193,23 @@ hipError_t launch_dot2(const double* a, const double* b, const double* c, const 
   return hipGetLastError();
 }
 
-hipError_t launch_widen_dot(const float* z32, double* z, const double* r, long long n, double* partial, double* out,
-                            hipStream_t st) {
+hipError_t launch_dot_rz32(const float* z32, const double* r, long long n, double* partial, double* out,
+                           hipStream_t st) {
   const int parts = reduction_parts();
-  hipLaunchKernelGGL(widen_dot_kernel, dim3(parts), dim3(kRedThreads), 0, st, z32, z, r, n, partial);
+  hipLaunchKernelGGL(dot_rz32_kernel, dim3(parts), dim3(kRedThreads), 0, st, z32, r, n, partial);
   hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, long long n,
-                            double* sc, double* partial, float* r32, hipStream_t st) {
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, const double* z, const float* z32,
+                            long long n, double* sc, double* partial, float* r32, hipStream_t st) {
   const int parts = reduction_parts();
-  hipLaunchKernelGGL(cg_update_kernel, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z, n, sc, partial, r32);
+  if (z32)
+    hipLaunchKernelGGL(cg_update_kernel<float>, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z32, n, sc, partial,
+                       r32);
+  else
+    hipLaunchKernelGGL(cg_update_kernel<double>, dim3(parts), dim3(kRedThreads), 0, st, x, r, p, q, z, n, sc, partial,
+                       r32);
   hipLaunchKernelGGL(finalize2_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, sc + kScRR);
   return hipGetLastError();
 }
@@ -222,13 +219,12 @@ hipError_t launch_cg_beta(double* sc, int flexible, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cg_x_step(double* x, const double* p, long long n, const double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(cg_x_step_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, p, n, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_direction(double* p, const double* z, long long n, const double* sc, hipStream_t st) {
-  hipLaunchKernelGGL(cg_direction_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, z, n, sc);
+hipError_t launch_cg_direction(double* p, const double* z, const float* z32, long long n, const double* sc,
+                               hipStream_t st) {
+  if (z32)
+    hipLaunchKernelGGL(cg_direction_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st, p, z32, n, sc);
+  else
+    hipLaunchKernelGGL(cg_direction_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st, p, z, n, sc);
   return hipGetLastError();
 }
 
