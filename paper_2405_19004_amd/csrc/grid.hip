@@ -430,10 +430,13 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
 // ----------------------------------------------------------- prolongation
 
 // Coarse cells per tile.
+// Coarse cells per tile and threads: 3D tiles of degree <= 4 span 2kC ~ 16 fine nodes per axis, so
+// the last stage (one thread per fine column) fills a 256-thread workgroup (measured at k = 4:
+// 31 us against 44 us for C = 1 with 128 threads on 64^3 cells).
 template <int D, int K>
 struct ProShape {
-  static constexpr int C = K == 1 ? (D == 2 ? 16 : 4) : K == 2 ? (D == 2 ? 8 : 2) : (D == 2 ? 4 : 1);
-  static constexpr int NT = 128;
+  static constexpr int C = D == 2 ? (K == 1 ? 16 : K == 2 ? 8 : 4) : (K == 1 ? 8 : K == 2 ? 4 : K <= 4 ? 2 : 1);
+  static constexpr int NT = D == 3 && K <= 4 ? 256 : 128;
 };
 
 // x_fine += P e_coarse.  Tile: coarse cells [C t, C (t+1)) per axis, fine outputs
@@ -643,7 +646,7 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
 // P1 is used once).  Fine boundary nodes count as 0; coarse boundary nodes are written 0.
 //  * restrict_plane_kernel: one workgroup per (fine plane, TX x TX coarse-column tile) reduces
 //    the plane along x0 and x1 (LDS) into T[zf][J1][J0] (nc x nc per fine plane);
-//  * restrict_z_kernel: one thread per coarse node reduces T along x2.
+//  * restrict_z_kernel: one thread per coarse column (and chunk of cells) streams T along x2.
 // Every launch is fully parallel (no chain of dependent planes inside a workgroup), the fine
 // vector is read once and the intermediate is a quarter of it.
 
@@ -720,33 +723,56 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   }
 }
 
-// Workgroup = 64 x 4 coarse nodes (x0 fastest) of one coarse plane zc = blockIdx.z; the plane's
-// cell C and node class a are uniform, so are the coefficients and the fine planes read.
+// Workgroup = 64 x 4 coarse columns (x0 fastest); blockIdx.z = a chunk of cz coarse cells along x2.
+// A thread walks its column through the chunk: each fine plane of a cell's run is read once and
+// adds P[q][a] times its value to the cell's k+1 coarse nodes; a cell's last node is carried to the
+// next cell's first.  The chunk's first vertex takes the run of the cell before the chunk (one run
+// of halo).  Sums run in the same order as the node-by-node definition (previous run, then own run).
 template <int K, typename T>
-__global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc) {
+__global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc,
+                                                        int cz) {
   constexpr int NP = K + 1, RUN = 2 * K;
-  const int gx = blockIdx.x * 64 + threadIdx.x, gy = blockIdx.y * 4 + threadIdx.y, zc = blockIdx.z;
+  using CT = gen::CellTables<T, K>;
+  const int gx = blockIdx.x * 64 + threadIdx.x, gy = blockIdx.y * 4 + threadIdx.y;
   if (gx >= nc || gy >= nc) return;
+  const int ncc = (nc - 1) / K;  // coarse cells along x2
+  const int C0 = blockIdx.z * cz, C1 = min(C0 + cz, ncc);
   const long long nc2 = (long long)nc * nc;
   const unsigned off = (unsigned)(gy * nc + gx) * (unsigned)sizeof(T);  // within a plane
-  T s = T(0);
-  if (zc > 0 && zc < nc - 1 && gy > 0 && gy < nc - 1 && gx > 0 && gx < nc - 1) {
-    using CT = gen::CellTables<T, K>;
-    const int C = zc / K, a = zc - C * K;
-    if (a == 0) {
+  const bool col = gx > 0 && gx < nc - 1 && gy > 0 && gy < nc - 1;     // else a boundary column: 0
+  T carry = T(0);  // the previous cell's contribution to the current cell's first node
+  if (C0 > 0) {
 #pragma unroll
-      for (int q = 0; q < RUN; ++q) {
-        const int zf = RUN * (C - 1) + q;  // >= 0 since zc > 0 means C >= 1 here
-        if (zf >= 1) s = fma(CT::P[q * NP + K], ld_lane(tz + zf * nc2, off), s);
-      }
+    for (int q = 0; q < RUN; ++q) {
+      const int zf = RUN * (C0 - 1) + q;
+      if (zf >= 1) carry = fma(CT::P[q * NP + K], ld_lane(tz + zf * nc2, off), carry);
     }
+  }
+  for (int C = C0; C < C1; ++C) {
+    T s[NP];
+    s[0] = carry;
+#pragma unroll
+    for (int a = 1; a < NP; ++a) s[a] = T(0);
 #pragma unroll
     for (int q = 0; q < RUN; ++q) {
       const int zf = RUN * C + q;
-      if (zf >= 1 && zf <= nf - 2) s = fma(CT::P[q * NP + a], ld_lane(tz + zf * nc2, off), s);
+      if (zf >= 1 && zf <= nf - 2) {
+        const T v = ld_lane(tz + zf * nc2, off);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;  // the run's first fine node is the coarse vertex itself
+          s[a] = fma(CT::P[q * NP + a], v, s[a]);
+        }
+      }
     }
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      const int zc = K * C + a;
+      st_lane(rc + zc * nc2, off, col && zc > 0 ? s[a] : T(0));
+    }
+    carry = s[K];
   }
-  st_lane(rc + zc * nc2, off, s);
+  if (C1 == ncc) st_lane(rc + (nc - 1) * nc2, off, T(0));  // the last coarse plane is a boundary plane
 }
 
 // ------------------------------------------------------- boundary and rhs
@@ -944,6 +970,7 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
   const int tiles = ceil_div(ncc, S::C);
   const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
   const long long n1dc = (long long)K * ncc + 1;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((prolong_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf,
                      n1dc, fine.n1d, tiles);
   return hipGetLastError();
@@ -964,8 +991,16 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
     hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)(nf - 2)), dim3(S::NT),
                        0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
     if (nc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32)) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)nc),
-                       dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc);
+    // chunks of coarse cells along x2: about 2048 waves in all
+    const int ncc_z = (nc - 1) / K;
+    const long long cols = (long long)nc * nc;
+    int chunks = (int)((2048LL * 64 + cols - 1) / cols);
+    if (chunks > ncc_z) chunks = ncc_z;
+    if (chunks < 1) chunks = 1;
+    const int cz = (ncc_z + chunks - 1) / chunks;
+    chunks = (ncc_z + cz - 1) / cz;
+    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)chunks),
+                       dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, cz);
   } else {
     // grid x: 256-thread blocks over one output plane (rows flattened)
     if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
