@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--serve", type=int, default=120, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serve", type=int, default=2000, help="requests in the serving run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-table7", action="store_true",
                     help="skip the mixed/double solves at the sizes of Table 7 (135M-721M DoFs)")
@@ -94,13 +94,19 @@ def event_time(fn, stream, reps):
     return s.elapsed_time(e) / reps / 1e3
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def serving_run(v, n_requests, max_active=16, budget=64 << 30):
     """Continuous-batching server over a seeded stream of mixed (d, k, level) requests.
 
     Right-hand sides are assembled on the device before the clock starts.  First
     a closed-loop run (every request present at t = 0) measures capacity; then
     the same requests arrive as a Poisson process at 80 % of that capacity and
-    latency (arrival -> completion) is recorded per request.
+    latency (arrival -> completion) is recorded per request; last, a closed-loop
+    run of the same stream with plain FP64 solves gives the FP64 capacity.
     """
     import synth
     trace = synth.serving_trace(seed=3, n_requests=n_requests, rate_per_s=1.0)
@@ -118,7 +124,7 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
     import torch
     torch.cuda.synchronize()
 
-    def run(scale):
+    def run(scale, mode=v.VPS_SOLVE_MIXED):
         srv = v.vps_server_create(budget, max_active)
         t0 = time.perf_counter()
         pending = list(trace)
@@ -129,13 +135,12 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
                 while pending and pending[0]["arrival"] * scale <= now:
                     r = pending.pop(0)
                     t = v.vps_server_submit(srv, r["d"], r["k"], r["level"], r["b"].data_ptr(), r["x"].data_ptr(),
-                                            RTOL, v.VPS_SOLVE_MIXED, 50)
+                                            RTOL, mode, 50)
                     arrive[t] = r["arrival"] * scale
                 active, queued = v.vps_server_step(srv)
                 now = time.perf_counter() - t0
-                for t in arrive:
-                    if t not in done and v.vps_server_poll(srv, t)[0]:
-                        done[t] = now
+                for t in v.vps_server_completed(srv):
+                    done[t] = now
                 if not pending and len(done) == len(trace):
                     break
                 if active == 0 and queued == 0 and pending:
@@ -150,12 +155,15 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
     capacity = len(trace) / span0
     rate = 0.8 * capacity
     span1, lat1 = run(1.0 / rate)
+    span64, lat64 = run(0.0, v.VPS_SOLVE_FP64)  # the same stream, plain FP64 solves, closed loop
     q = lambda a, p: a[min(len(a) - 1, int(round(p * (len(a) - 1))))]
     return {"requests": len(trace), "total_dofs": total, "closed_loop_req_per_s": capacity,
             "closed_loop_dof_per_s": total / span0, "closed_loop_p50_ms": 1e3 * q(lat0, 0.5),
             "closed_loop_p99_ms": 1e3 * q(lat0, 0.99), "arrival_rate_per_s": rate,
             "p50_ms": 1e3 * q(lat1, 0.5), "p99_ms": 1e3 * q(lat1, 0.99), "mean_ms": 1e3 * sum(lat1) / len(lat1),
-            "dof_per_s": total / span1, "max_active": max_active}
+            "dof_per_s": total / span1, "max_active": max_active,
+            "fp64_closed_loop_req_per_s": len(trace) / span64, "fp64_closed_loop_dof_per_s": total / span64,
+            "mixed_vs_fp64_closed_loop_speedup": span64 / span0}
 
 
 # Table 7 (3D, manufactured solution prod sin(pi x_i), residual reduction 1e-9): degree,
@@ -409,13 +417,17 @@ def main():
                                         "hbm_gbps": bytes64 / t64 / 1e9, "hbm_frac": bytes64 / t64 / PEAK_HBM,
                                         "alu_tflops": flops / t64 / 1e12, "alu_frac": flops / t64 / PEAK_FP64}
     P.close()
+    progress("headline solve, components and colour-pass roofline done")
 
     if a.serve > 0:
         out["serving"] = serving_run(v, a.serve)
+        progress("serving run done (%d requests)" % a.serve)
     if not a.no_table7:
         out["table7"] = table7_run(v, torch)
+        progress("Table 7 problems done")
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, its[-1] + 1)
+        progress("CPU oracle baseline done")
     print(json.dumps(out))
 
 

@@ -237,6 +237,12 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued);
 /* *done = 1 when the request finished (then *stats holds its result).  Host-only. */
 int vps_server_poll(vps_server* s, long long ticket, int* done, vps_solve_stats_t* stats);
 
+/* Tickets of requests finished since the previous call, in completion order: up to cap of them
+ * are written to tickets (host array) and removed from the list, *n receives how many were
+ * written.  Lets a caller with many requests in flight find completions without polling each
+ * ticket.  Host-only; VPS_EINVAL on a null server or n, or on cap > 0 with a null array. */
+int vps_server_completed(vps_server* s, long long* tickets, int cap, int* n);
+
 /* Device bytes currently held by admitted requests and cached hierarchies. */
 int vps_server_memory(vps_server* s, size_t* in_use, size_t* cached);
 

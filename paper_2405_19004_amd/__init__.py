@@ -73,6 +73,7 @@ _SIGS = {
     "vps_server_submit": (_I, [_P, _I, _I, _I, _P, _P, ctypes.c_double, _I, _I, ctypes.POINTER(_LL)]),
     "vps_server_step": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "vps_server_poll": (_I, [_P, _LL, ctypes.POINTER(_I), ctypes.POINTER(SolveStats)]),
+    "vps_server_completed": (_I, [_P, ctypes.POINTER(_LL), _I, ctypes.POINTER(_I)]),
     "vps_server_memory": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "vps_server_destroy": (_I, [_P]),
 }
@@ -252,6 +253,18 @@ def vps_server_poll(s, ticket):
     st = SolveStats()
     _call("vps_server_poll", s, ticket, ctypes.byref(done), ctypes.byref(st))
     return bool(done.value), st
+
+
+def vps_server_completed(s, cap=4096):
+    """Tickets finished since the previous call (completion order)."""
+    out = []
+    buf = (_LL * cap)()
+    n = _I()
+    while True:
+        _call("vps_server_completed", s, buf, cap, ctypes.byref(n))
+        out.extend(buf[i] for i in range(n.value))
+        if n.value < cap:
+            return out
 
 
 def vps_server_memory(s):

@@ -62,6 +62,7 @@ struct vps_server {
   std::vector<Request*> active;
   std::map<long long, Request*> all;
   std::list<Slot> idle;  // cached hierarchies, most recently used at the front
+  std::deque<long long> completed;  // finished tickets not yet reported by vps_server_completed
   size_t in_use = 0, cached = 0;
   std::map<std::tuple<int, int, int>, hipStream_t> streams;  // per (dim, degree, mode)
 };
@@ -130,8 +131,9 @@ void release(vps_server* S, Request* r) {
   r->slot = Slot();
 }
 
-void finish(Request* r) {
+void finish(vps_server* S, Request* r) {
   r->done = true;
+  S->completed.push_back(r->id);
   r->stats.iterations = r->cs.stats.iterations;
   r->stats.rel_residual = r->cs.stats.rel_residual;
   r->stats.true_rel_residual = r->cs.stats.true_rel_residual;
@@ -192,7 +194,7 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
     if (r->cs.done) {
       st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
       if (st.code) return sfail(st.code, st.msg);
-      finish(r);
+      finish(s, r);
       release(s, r);
       continue;
     }
@@ -213,7 +215,7 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
     if (r->cs.done) {
       st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
       if (st.code) return sfail(st.code, st.msg);
-      finish(r);
+      finish(s, r);
       release(s, r);
     } else {
       still.push_back(r);
@@ -243,6 +245,17 @@ int vps_server_poll(vps_server* s, long long ticket, int* done, vps_solve_stats_
   if (it == s->all.end()) return sfail(VPS_EINVAL, "unknown ticket");
   *done = it->second->done ? 1 : 0;
   if (it->second->done && stats) *stats = it->second->stats;
+  return VPS_OK;
+}
+
+int vps_server_completed(vps_server* s, long long* tickets, int cap, int* n) {
+  if (!s || !n || cap < 0 || (cap > 0 && !tickets)) return sfail(VPS_EINVAL, "bad arguments");
+  int k = 0;
+  while (k < cap && !s->completed.empty()) {
+    tickets[k++] = s->completed.front();
+    s->completed.pop_front();
+  }
+  *n = k;
   return VPS_OK;
 }
 

@@ -43,13 +43,17 @@ def _serve(reqs, budget, max_active, mode):
             x = torch.full_like(b, 5.0)
             xs.append(x)
             tickets.append(vps.vps_server_submit(srv, d, k, L, b.data_ptr(), x.data_ptr(), 1e-8, mode, 50))
+        finished = []
         for _ in range(10000):
             active, queued = vps.vps_server_step(srv)
             in_use, cached = vps.vps_server_memory(srv)
             peak = max(peak, in_use + cached)
+            finished += vps.vps_server_completed(srv, cap=3)  # small cap: several calls per tick
             if active == 0 and queued == 0:
                 break
         stats = [vps.vps_server_poll(srv, t) for t in tickets]
+        # every ticket is reported exactly once, and only once it is done
+        assert sorted(finished) == sorted(tickets) and vps.vps_server_completed(srv) == []
     finally:
         vps.vps_server_destroy(srv)
     return xs, stats, peak
