@@ -78,8 +78,9 @@ Plan plan(int dim, int k, int L, unsigned flags) {
     pl.sizes.push_back(N1 * 8);
   }
   if (solver) {
+    // r, z, p, q; z only with the FP64 hierarchy: a mixed solve reads the FP32 V-cycle output
     const size_t N = (size_t)level_nodes(dim, k, L);
-    for (int i = 0; i < 4; ++i) pl.sizes.push_back(N * 8);  // r z p q
+    for (int i = 0; i < (h64 ? 4 : 3); ++i) pl.sizes.push_back(N * 8);
   }
   pl.sizes.push_back(kScCount * 8);
   pl.sizes.push_back(2 * (size_t)reduction_parts() * 8);
@@ -173,7 +174,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   }
   if (solver) {
     p->r = (double*)p->allocs[idx++];
-    p->z = (double*)p->allocs[idx++];
+    if (h64) p->z = (double*)p->allocs[idx++];
     p->p = (double*)p->allocs[idx++];
     p->q = (double*)p->allocs[idx++];
   }
@@ -267,13 +268,13 @@ Status vcycle(Problem* p, int prec, const void* bL, void* xL) { return vcycle_to
 namespace {
 
 // *out_slot <- ||v||^2 over the interior nodes of the finest level (v in `prec`); the FP64 copy
-// goes to p->q.  Sets p->bad on a non-finite entry.
+// goes to p->q (p->p is scratch: FMG does not run CG).  Sets p->bad on a non-finite entry.
 Status interior_norm2(Problem* p, int prec, const void* v, double* out_slot) {
   const LevelGeom& g = p->geom(p->L);
   const double* src = static_cast<const double*>(v);
   if (prec == 1) {
-    VPS_HIP(launch_cast(1, v, p->z, p->lv[p->L].N, p->stream));
-    src = p->z;
+    VPS_HIP(launch_cast(1, v, p->p, p->lv[p->L].N, p->stream));
+    src = p->p;
   }
   VPS_HIP(launch_copy_interior_norm(p->dim, g.n1d, src, p->q, p->partial, out_slot, p->bad, p->stream));
   return Status::ok();
@@ -288,8 +289,8 @@ Status residual_norm2(Problem* p, int prec, const void* b, const void* x, double
     VPS_HIP(launch_operator(g, 0, x, b, p->q, p->stream));
   } else {
     void* r32 = p->lv[p->L].r[1];
-    if (!r32) {  // single-level hierarchy: FP32 residual in the front half of z
-      r32 = p->z;
+    if (!r32) {  // single-level hierarchy: FP32 residual in the front half of p (scratch here)
+      r32 = p->p;
       VPS_HIP(launch_fill(1, r32, N, 0.0, p->stream));
     }
     VPS_HIP(launch_operator(g, 1, x, b, r32, p->stream));
