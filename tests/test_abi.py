@@ -69,6 +69,26 @@ def test_footprint_and_validation_need_no_device():
     with pytest.raises(v.VpsError):
         v.vps_footprint_bytes(3, 7, 20)  # N >= 2^40
     assert "dim" in v.last_error() or "large" in v.last_error() or v.last_error()
+    # a mixed-only hierarchy has no FP64 z (the mixed CG reads the FP32 V-cycle output): adding the
+    # FP64 hierarchy adds its level buffers and z, i.e. the FP64-only footprint less r, p, q and the
+    # scalar block, partial sums and flag (allocations rounded to 256 bytes)
+    m = v.vps_footprint_bytes(3, 4, 6, v.VPS_FLAG_FP32_HIERARCHY)
+    ru = lambda x: (x + 255) // 256 * 256
+    assert b - m == a - 3 * ru(8 * n) - ru(16 * 8) - ru(2 * 1024 * 8) - 256
+
+
+def test_server_completed_validates_on_host():
+    import ctypes
+    import paper_2405_19004_amd as v
+    n = ctypes.c_int(-1)
+    assert v.lib().vps_server_completed(None, None, 0, ctypes.byref(n)) == v.VPS_EINVAL
+    s = v.vps_server_create(1 << 20, 4)
+    try:
+        assert v.vps_server_completed(s) == []  # nothing finished yet
+        assert v.lib().vps_server_completed(s, None, 4, ctypes.byref(n)) == v.VPS_EINVAL  # cap > 0, no array
+        assert v.lib().vps_server_completed(s, None, 0, None) == v.VPS_EINVAL
+    finally:
+        v.vps_server_destroy(s)
 
 
 def test_server_rejects_oversize_request_on_host():
