@@ -31,6 +31,8 @@ RTOL = 1e-8
 PEAK_FP32 = 157.3e12  # MI355X published FP32 vector peak
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12  # MI355X HBM3E
+# LDS: 32 banks of 4 bytes per clock and compute unit, 256 compute units at 2.4 GHz
+PEAK_LDS = 32 * 4 * 256 * 2.4e9
 
 
 def colour_pass_flops(d, k):
@@ -56,6 +58,19 @@ def colour_pass_bytes(d, k, es):
     """Algorithmic HBM bytes of one patch: read x closure + b interior, write x interior."""
     n, m = 2 * k + 1, 2 * k - 1
     return es * (n ** d + 2 * m ** d)
+
+
+def colour_pass_lds_bytes_3d(k, es, ppw):
+    """LDS bytes one patch moves in the 3D colour pass that runs the closure through LDS (every
+    write and read of its stages): closure rows in, then per stage the lines read and written."""
+    n, m = 2 * k + 1, 2 * k - 1
+    words = n * n * (2 * k * ppw + 1) / ppw    # closure segment written (shared faces once)
+    words += n ** 3 + 2 * n * n * m            # x0: closure lines in, M and A rows out
+    words += 2 * n * n * m + 2 * n * m * m     # x1
+    words += 2 * n * m * m + m ** 3            # x2 residual and S^T along x2
+    words += 2 * m ** 3 * 3                    # S^T x1; S^T x0, 1/lambda, S x0; S x1
+    words += 2 * m ** 3                        # S x2, and the old interior values from the closure
+    return es * words
 
 
 def smoother_source_hash():
@@ -387,6 +402,7 @@ def main():
     patches = sum(info.color_count[c] for c in range(8)) / 8
     flops = colour_pass_flops(D, K) * patches
     bytes_ = colour_pass_bytes(D, K, 4) * patches
+    lds_bytes = colour_pass_lds_bytes_3d(K, 4, 2) * patches
     traffic = None
     tf = os.path.join(ROOT, "profiles", "colour_pass_3d_q4_fp32_traffic.json")
     if os.path.exists(tf):
@@ -402,7 +418,9 @@ def main():
               "alu": {"achieved_tflops": flops / t_all / 1e12, "peak_tflops": PEAK_FP32 / 1e12,
                       "frac": flops / t_all / PEAK_FP32},
               "hbm": {"achieved_gbps": bytes_ / t_all / 1e9, "peak_gbps": PEAK_HBM / 1e9,
-                      "frac": bytes_ / t_all / PEAK_HBM}}
+                      "frac": bytes_ / t_all / PEAK_HBM},
+              "lds": {"achieved_tbps": lds_bytes / t_all / 1e12, "peak_tbps": PEAK_LDS / 1e12,
+                      "frac": lds_bytes / t_all / PEAK_LDS, "bytes_per_launch": lds_bytes}}
     if t_hbm >= t_alu:
         out["roofline"] = dict(bound="hbm", achieved=bytes_ / t_all / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
                                frac=bytes_ / t_all / PEAK_HBM, **common)

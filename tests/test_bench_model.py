@@ -54,3 +54,13 @@ def test_patch_eigenvectors_are_even_or_odd(k):
 def test_flop_model_at_degree_4():
     assert bench.colour_pass_flops(3, 4) == 53201
     assert bench.colour_pass_bytes(3, 4, 4) == 4 * (9 ** 3 + 2 * 7 ** 3)
+
+
+def test_lds_traffic_model_3d_q4():
+    """LDS words per patch of the closure-through-LDS colour pass (3D Q4, two patches per
+    workgroup): closure 81 * 17 / 2, then per stage lines in and out, summed by hand."""
+    import bench
+    by_hand = 81 * 17 / 2 + (729 + 1134) + (1134 + 882) + (882 + 343) + 6 * 343 + 2 * 343
+    assert by_hand == 8536.5
+    assert bench.colour_pass_lds_bytes_3d(4, 4, 2) == 4 * by_hand
+    assert bench.colour_pass_lds_bytes_3d(4, 8, 2) == 8 * by_hand
