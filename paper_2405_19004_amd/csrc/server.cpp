@@ -16,10 +16,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <deque>
+#include <functional>
 #include <list>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -52,6 +56,86 @@ unsigned flags_for(int mode) {
   return mode == VPS_SOLVE_MIXED ? VPS_FLAG_FP32_HIERARCHY : VPS_FLAG_FP64_HIERARCHY;
 }
 
+// Host threads that issue the launches of different request groups at once: each group has its
+// own stream and is handled by one thread, so the order of every stream's work is the order of a
+// single-threaded tick (and so are the results); only the host time of issuing overlaps.
+class LaunchPool {
+ public:
+  explicit LaunchPool(int workers) {
+    for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { loop(); });
+  }
+  ~LaunchPool() {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      stop_ = true;
+    }
+    wake_.notify_all();
+    for (std::thread& t : threads_) t.join();
+  }
+  // f(0) .. f(n-1), spread over the workers and the calling thread; returns when all have run
+  void run(int n, const std::function<void(int)>& f) {
+    if (threads_.empty() || n <= 1) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> l(m_);
+      job_ = &f;
+      n_ = n;
+      next_ = 0;
+      done_ = 0;
+      device_ = dev;
+      ++gen_;
+    }
+    wake_.notify_all();
+    work();
+    std::unique_lock<std::mutex> l(m_);
+    finished_.wait(l, [this] { return done_ == n_; });
+    job_ = nullptr;
+  }
+
+ private:
+  void work() {
+    for (;;) {
+      int i;
+      const std::function<void(int)>* f;
+      {
+        std::lock_guard<std::mutex> l(m_);
+        if (!job_ || next_ >= n_) return;
+        i = next_++;
+        f = job_;
+      }
+      (*f)(i);
+      std::lock_guard<std::mutex> l(m_);
+      if (++done_ == n_) finished_.notify_all();
+    }
+  }
+  void loop() {
+    unsigned seen = 0;
+    for (;;) {
+      int dev;
+      {
+        std::unique_lock<std::mutex> l(m_);
+        wake_.wait(l, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        dev = device_;
+      }
+      if (hipSetDevice(dev) != hipSuccess) (void)hipGetLastError();  // the caller's device
+      work();
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::mutex m_;
+  std::condition_variable wake_, finished_;
+  const std::function<void(int)>* job_ = nullptr;
+  int n_ = 0, next_ = 0, done_ = 0, device_ = 0;
+  unsigned gen_ = 0;
+  bool stop_ = false;
+};
+
 }  // namespace
 
 struct vps_server {
@@ -65,6 +149,7 @@ struct vps_server {
   std::deque<long long> completed;  // finished tickets not yet reported by vps_server_completed
   size_t in_use = 0, cached = 0;
   std::map<std::tuple<int, int, int>, hipStream_t> streams;  // per (dim, degree, mode)
+  LaunchPool* pool = nullptr;
 };
 
 namespace {
@@ -150,6 +235,9 @@ int vps_server_create(size_t hbm_budget_bytes, int max_active, void* hip_stream,
   vps_server* s = new vps_server();
   s->budget = hbm_budget_bytes;
   s->max_active = max_active;
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int workers = hw > 2 ? (int)std::min(hw - 1, 7u) : 0;  // plus the calling thread
+  s->pool = new LaunchPool(workers);
   *out = s;
   return VPS_OK;
 }
@@ -200,10 +288,22 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
     }
     s->active.push_back(r);
   }
-  // one CG iteration for every active request (groups overlap on their streams)
-  for (Request* r : s->active) {
-    vps::Status st = vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
-    if (st.code) return sfail(st.code, st.msg);
+  // one CG iteration for every active request (groups overlap on their streams; each group's
+  // launches are issued by one host thread)
+  {
+    std::map<std::tuple<int, int, int>, std::vector<Request*>> by_stream;
+    for (Request* r : s->active) by_stream[std::make_tuple(r->dim, r->k, r->mode)].push_back(r);
+    std::vector<std::vector<Request*>*> lists;
+    for (auto& kv : by_stream) lists.push_back(&kv.second);
+    std::vector<vps::Status> res(lists.size());
+    s->pool->run((int)lists.size(), [&](int i) {
+      for (Request* r : *lists[i]) {
+        res[i] = vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
+        if (res[i].code) return;
+      }
+    });
+    for (const vps::Status& st : res)
+      if (st.code) return sfail(st.code, st.msg);
   }
   for (auto& kv : s->streams)
     if (hipStreamSynchronize(kv.second) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
@@ -222,16 +322,24 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
       groups[std::make_tuple(r->dim, r->k, r->mode)].push_back(r);
     }
   }
-  // preconditioner: one batched V-cycle per group, colour passes packed across its requests
-  for (auto& kv : groups) {
-    std::vector<vps::Problem*> ps;
-    for (Request* r : kv.second) ps.push_back(r->slot.prob);
-    vps::Status st = vps::precondition_group(ps.data(), (int)ps.size(), std::get<2>(kv.first));
-    if (st.code) return sfail(st.code, st.msg);
-    for (Request* r : kv.second) {
-      st = vps::pcg_after_precond(r->slot.prob, r->mode);
+  // preconditioner: one batched V-cycle per group, colour passes packed across its requests; the
+  // groups are issued from parallel host threads
+  {
+    std::vector<std::pair<const std::tuple<int, int, int>, std::vector<Request*>>*> glist;
+    for (auto& kv : groups) glist.push_back(&kv);
+    std::vector<vps::Status> res(glist.size());
+    s->pool->run((int)glist.size(), [&](int i) {
+      std::vector<vps::Problem*> ps;
+      for (Request* r : glist[i]->second) ps.push_back(r->slot.prob);
+      res[i] = vps::precondition_group(ps.data(), (int)ps.size(), std::get<2>(glist[i]->first));
+      if (res[i].code) return;
+      for (Request* r : glist[i]->second) {
+        res[i] = vps::pcg_after_precond(r->slot.prob, r->mode);
+        if (res[i].code) return;
+      }
+    });
+    for (const vps::Status& st : res)
       if (st.code) return sfail(st.code, st.msg);
-    }
   }
   s->active.swap(still);
   if (n_active) *n_active = (int)s->active.size();
@@ -268,6 +376,7 @@ int vps_server_memory(vps_server* s, size_t* in_use, size_t* cached) {
 
 int vps_server_destroy(vps_server* s) {
   if (!s) return VPS_OK;
+  delete s->pool;
   for (auto& kv : s->streams) (void)hipStreamSynchronize(kv.second);
   for (Request* r : s->active) free_slot(r->slot);
   for (Slot& sl : s->idle) free_slot(sl);
