@@ -236,7 +236,10 @@ int vps_server_create(size_t hbm_budget_bytes, int max_active, void* hip_stream,
   s->budget = hbm_budget_bytes;
   s->max_active = max_active;
   const unsigned hw = std::thread::hardware_concurrency();
-  const int workers = hw > 2 ? (int)std::min(hw - 1, 7u) : 0;  // plus the calling thread
+#ifndef VPS_SERVER_THREADS
+#define VPS_SERVER_THREADS 7u
+#endif
+  const int workers = hw > 2 ? (int)std::min(hw - 1, (unsigned)VPS_SERVER_THREADS) : 0;  // plus the calling thread
   s->pool = new LaunchPool(workers);
   *out = s;
   return VPS_OK;
