@@ -515,7 +515,7 @@ Status precondition_group(Problem* const* ps, int n, int mode) {
   return Status::ok();
 }
 
-Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) {
+Status pcg_begin_launch(Problem* p, int mode, const double* b, double* x, CgState* cs) {
   if (!p->r) return Status{-1, "problem was created without solver vectors"};
   if (!p->has(mode == 0 ? 0 : 1)) return Status{-1, "solve mode needs the matching hierarchy flag"};
   const long long N = p->lv[p->L].N;
@@ -523,28 +523,41 @@ Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) 
   VPS_HIP(hipMemsetAsync(p->bad, 0, sizeof(int), p->stream));
   VPS_HIP(launch_copy_interior_norm(p->dim, p->lv[p->L].g.n1d, b, p->r, p->partial, p->sc + kScBB, p->bad, p->stream));
   VPS_HIP(launch_fill(0, x, N, 0.0, p->stream));
+  if (mode == 1) VPS_HIP(launch_cast(0, p->r, p->lv[p->L].b[1], N, p->stream));  // the FP32 V-cycle's input
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_bad, p->bad, sizeof(int), hipMemcpyDeviceToHost, p->stream));
-  VPS_HIP(hipStreamSynchronize(p->stream));
+  return Status::ok();
+}
+
+Status pcg_begin_check(Problem* p, CgState* cs) {
   cs->bb = p->host_sc[kScBB];
   if (*p->host_bad || !std::isfinite(cs->bb)) {
     cs->done = true;
     cs->stats.status = -6;
-    return Status::ok();
-  }
-  if (cs->bb == 0.0) {
+  } else if (cs->bb == 0.0) {
     cs->done = true;
     cs->stats.rel_residual = 0.0;
-    return Status::ok();
   }
-  if (mode == 1) VPS_HIP(launch_cast(0, p->r, p->lv[p->L].b[1], N, p->stream));
-  VPS_TRY(precondition(p, mode));
+  return Status::ok();
+}
+
+Status pcg_begin_after_precond(Problem* p, int mode) {
+  const long long N = p->lv[p->L].N;
   VPS_HIP(launch_cg_beta(p->sc, 0, p->stream));  // rz <- rz_new (beta unused here)
   if (mode == 1)
     VPS_HIP(launch_cast(1, cg_z32(p, mode), p->p, N, p->stream));  // p = z, widened exactly
   else
     VPS_HIP(hipMemcpyAsync(p->p, p->z, N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
   return Status::ok();
+}
+
+Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs) {
+  VPS_TRY(pcg_begin_launch(p, mode, b, x, cs));
+  VPS_HIP(hipStreamSynchronize(p->stream));
+  VPS_TRY(pcg_begin_check(p, cs));
+  if (cs->done) return Status::ok();
+  VPS_TRY(precondition(p, mode));
+  return pcg_begin_after_precond(p, mode);
 }
 
 Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
@@ -602,14 +615,27 @@ Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState*
   return pcg_after_precond(p, mode);
 }
 
-Status pcg_end(Problem* p, const double* b, double* x, CgState* cs) {
-  const long long N = p->lv[p->L].N;
+Status pcg_end_launch(Problem* p, const double* b, const double* x, const CgState* cs, bool* pending) {
+  *pending = false;
   if (cs->stats.status == -6 || cs->bb == 0.0) return Status::ok();
+  const long long N = p->lv[p->L].N;
   VPS_HIP(launch_operator(p->geom(p->L), 0, x, b, p->q, p->stream));  // q = b - A x (interior)
   VPS_HIP(launch_dot2(p->q, p->q, nullptr, nullptr, N, p->partial, p->sc + kScTrue, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  VPS_HIP(hipStreamSynchronize(p->stream));
+  *pending = true;
+  return Status::ok();
+}
+
+void pcg_end_finish(const Problem* p, CgState* cs) {
   cs->stats.true_rel_residual = std::sqrt(p->host_sc[kScTrue] / cs->bb);
+}
+
+Status pcg_end(Problem* p, const double* b, double* x, CgState* cs) {
+  bool pending = false;
+  VPS_TRY(pcg_end_launch(p, b, x, cs, &pending));
+  if (!pending) return Status::ok();
+  VPS_HIP(hipStreamSynchronize(p->stream));
+  pcg_end_finish(p, cs);
   return Status::ok();
 }
 

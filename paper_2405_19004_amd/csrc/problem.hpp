@@ -100,6 +100,12 @@ struct CgState {
   SolveStats stats;
 };
 Status pcg_begin(Problem* p, int mode, const double* b, double* x, CgState* cs);
+// pcg_begin in parts, for callers that synchronise several problems at once: the launches up to
+// the copy of b.b to the host; after a synchronisation, the check of b (sets cs->done for a
+// non-finite or zero rhs); after the first preconditioner application, p = z.
+Status pcg_begin_launch(Problem* p, int mode, const double* b, double* x, CgState* cs);
+Status pcg_begin_check(Problem* p, CgState* cs);
+Status pcg_begin_after_precond(Problem* p, int mode);
 Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs);   // enqueue one iteration up to the norm copy
 Status pcg_iterate_finish(Problem* p, int mode, double rtol, int maxit, CgState* cs);  // after sync: decide, enqueue precond
 // pcg_iterate_finish in parts, for callers that precondition several problems together:
@@ -110,5 +116,9 @@ Status pcg_after_precond(Problem* p, int mode);  // z and r.z are ready: beta, n
 Status precondition(Problem* p, int mode);
 Status precondition_group(Problem* const* ps, int n, int mode);
 Status pcg_end(Problem* p, const double* b, double* x, CgState* cs);
+// pcg_end in parts: the true-residual launches (*pending = false when there is nothing to compute),
+// and after a synchronisation the relative true residual.
+Status pcg_end_launch(Problem* p, const double* b, const double* x, const CgState* cs, bool* pending);
+void pcg_end_finish(const Problem* p, CgState* cs);
 
 }  // namespace vps

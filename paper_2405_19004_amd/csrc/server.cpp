@@ -22,6 +22,7 @@
 #include <list>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -149,6 +150,7 @@ struct vps_server {
   std::deque<long long> completed;  // finished tickets not yet reported by vps_server_completed
   size_t in_use = 0, cached = 0;
   std::map<std::tuple<int, int, int>, hipStream_t> streams;  // per (dim, degree, mode)
+  std::map<std::tuple<int, int, int>, hipEvent_t> end_events;  // per stream: true residuals done
   LaunchPool* pool = nullptr;
 };
 
@@ -272,63 +274,108 @@ int vps_server_submit(vps_server* s, int dim, int degree, int level, const doubl
 
 int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
   if (!s) return sfail(VPS_EINVAL, "null server");
-  // admit in arrival order
-  while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+  using Key = std::tuple<int, int, int>;
+  auto key_of = [](const Request* r) { return std::make_tuple(r->dim, r->k, r->mode); };
+  // Run fn(request) for each list of `lists` on the launch pool (one list per stream).
+  auto on_pool = [&](std::vector<std::vector<Request*>*>& lists, const std::function<vps::Status(Request*)>& fn) {
+    std::vector<vps::Status> res(lists.size());
+    s->pool->run((int)lists.size(), [&](int i) {
+      for (Request* r : *lists[i]) {
+        res[i] = fn(r);
+        if (res[i].code) return;
+      }
+    });
+    for (const vps::Status& st : res)
+      if (st.code) return st;
+    return vps::Status::ok();
+  };
+  // admit in arrival order; the rhs check of a new request waits for this tick's synchronisation
+  std::vector<Request*> begun;
+  while (!s->queue.empty() && (int)(s->active.size() + begun.size()) < s->max_active) {
     Request* r = s->queue.front();
     int got = acquire(s, r);
     if (got < 0) return got;
     if (got == 0) break;
     s->queue.pop_front();
     r->admitted = true;
-    vps::Status st = vps::pcg_begin(r->slot.prob, r->mode, r->b, r->x, &r->cs);
+    vps::Status st = vps::pcg_begin_launch(r->slot.prob, r->mode, r->b, r->x, &r->cs);
     if (st.code) return sfail(st.code, st.msg);
-    if (r->cs.done) {
-      st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
-      if (st.code) return sfail(st.code, st.msg);
-      finish(s, r);
-      release(s, r);
-      continue;
-    }
-    s->active.push_back(r);
+    begun.push_back(r);
   }
   // one CG iteration for every active request (groups overlap on their streams; each group's
   // launches are issued by one host thread)
   {
-    std::map<std::tuple<int, int, int>, std::vector<Request*>> by_stream;
-    for (Request* r : s->active) by_stream[std::make_tuple(r->dim, r->k, r->mode)].push_back(r);
+    std::map<Key, std::vector<Request*>> by_stream;
+    for (Request* r : s->active) by_stream[key_of(r)].push_back(r);
     std::vector<std::vector<Request*>*> lists;
     for (auto& kv : by_stream) lists.push_back(&kv.second);
-    std::vector<vps::Status> res(lists.size());
-    s->pool->run((int)lists.size(), [&](int i) {
-      for (Request* r : *lists[i]) {
-        res[i] = vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
-        if (res[i].code) return;
-      }
+    vps::Status st = on_pool(lists, [](Request* r) {
+      return vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
     });
-    for (const vps::Status& st : res)
-      if (st.code) return sfail(st.code, st.msg);
+    if (st.code) return sfail(st.code, st.msg);
   }
   for (auto& kv : s->streams)
     if (hipStreamSynchronize(kv.second) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
+  // a request whose CG has ended launches its true residual (read back once this tick's
+  // preconditioners are issued) or, with nothing to compute, is finished now
+  std::vector<Request*> ending;
+  auto end_request = [&](Request* r) -> vps::Status {
+    bool pending = false;
+    vps::Status st = vps::pcg_end_launch(r->slot.prob, r->b, r->x, &r->cs, &pending);
+    if (st.code) return st;
+    if (pending) {
+      ending.push_back(r);
+    } else {
+      finish(s, r);
+      release(s, r);
+    }
+    return vps::Status::ok();
+  };
   std::vector<Request*> still;
-  std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
+  std::map<Key, std::vector<Request*>> groups;
   for (Request* r : s->active) {
     vps::Status st = vps::pcg_decide(r->slot.prob, r->mode, r->rtol, r->maxit, &r->cs);
     if (st.code) return sfail(st.code, st.msg);
     if (r->cs.done) {
-      st = vps::pcg_end(r->slot.prob, r->b, r->x, &r->cs);
+      st = end_request(r);
       if (st.code) return sfail(st.code, st.msg);
-      finish(s, r);
-      release(s, r);
     } else {
       still.push_back(r);
-      groups[std::make_tuple(r->dim, r->k, r->mode)].push_back(r);
+      groups[key_of(r)].push_back(r);
     }
   }
-  // preconditioner: one batched V-cycle per group, colour passes packed across its requests; the
-  // groups are issued from parallel host threads
+  std::vector<Request*> newcomers;
+  for (Request* r : begun) {
+    vps::Status st = vps::pcg_begin_check(r->slot.prob, &r->cs);
+    if (st.code) return sfail(st.code, st.msg);
+    if (r->cs.done) {
+      st = end_request(r);
+      if (st.code) return sfail(st.code, st.msg);
+    } else {
+      newcomers.push_back(r);
+      groups[key_of(r)].push_back(r);
+    }
+  }
+  // mark the end of the true-residual work on each stream that has some: the host waits for these
+  // marks, not for the preconditioners queued behind them
+  std::vector<hipEvent_t> marks;
   {
-    std::vector<std::pair<const std::tuple<int, int, int>, std::vector<Request*>>*> glist;
+    std::set<Key> keys;
+    for (Request* r : ending) keys.insert(key_of(r));
+    for (const Key& k : keys) {
+      hipEvent_t& ev = s->end_events[k];
+      if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+        return sfail(VPS_EHIP, "hipEventCreate failed");
+      }
+      if (hipEventRecord(ev, s->streams[k]) != hipSuccess) return sfail(VPS_EHIP, "hipEventRecord failed");
+      marks.push_back(ev);
+    }
+  }
+  // preconditioner: one batched V-cycle per group, colour passes packed across its requests (new
+  // requests take their first application with the others); groups issue from parallel threads
+  {
+    std::vector<std::pair<const Key, std::vector<Request*>>*> glist;
     for (auto& kv : groups) glist.push_back(&kv);
     std::vector<vps::Status> res(glist.size());
     s->pool->run((int)glist.size(), [&](int i) {
@@ -337,13 +384,23 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
       res[i] = vps::precondition_group(ps.data(), (int)ps.size(), std::get<2>(glist[i]->first));
       if (res[i].code) return;
       for (Request* r : glist[i]->second) {
-        res[i] = vps::pcg_after_precond(r->slot.prob, r->mode);
+        const bool fresh = r->cs.it == 0;  // first application: p = z
+        res[i] = fresh ? vps::pcg_begin_after_precond(r->slot.prob, r->mode)
+                       : vps::pcg_after_precond(r->slot.prob, r->mode);
         if (res[i].code) return;
       }
     });
     for (const vps::Status& st : res)
       if (st.code) return sfail(st.code, st.msg);
   }
+  for (hipEvent_t ev : marks)
+    if (hipEventSynchronize(ev) != hipSuccess) return sfail(VPS_EHIP, "event synchronize failed");
+  for (Request* r : ending) {
+    vps::pcg_end_finish(r->slot.prob, &r->cs);
+    finish(s, r);
+    release(s, r);
+  }
+  still.insert(still.end(), newcomers.begin(), newcomers.end());
   s->active.swap(still);
   if (n_active) *n_active = (int)s->active.size();
   if (n_queued) *n_queued = (int)s->queue.size();
@@ -383,6 +440,8 @@ int vps_server_destroy(vps_server* s) {
   for (auto& kv : s->streams) (void)hipStreamSynchronize(kv.second);
   for (Request* r : s->active) free_slot(r->slot);
   for (Slot& sl : s->idle) free_slot(sl);
+  for (auto& kv : s->end_events)
+    if (kv.second) (void)hipEventDestroy(kv.second);
   for (auto& kv : s->streams) (void)hipStreamDestroy(kv.second);
   for (auto& kv : s->all) delete kv.second;
   delete s;
