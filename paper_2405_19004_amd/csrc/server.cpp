@@ -7,10 +7,13 @@
 // later requests of the same shape, and evicted (least recently used first)
 // when a new shape needs their memory.  Requests of the same (dim, degree,
 // solve mode) form a group with one HIP stream; different groups overlap on
-// the device.  A tick enqueues one CG iteration for every active request,
-// waits, retires converged requests, then preconditions every group with one
-// batched V-cycle whose smoother colour passes are packed into one launch per
-// (level, colour) across the group's requests (levels may differ).  Each
+// the device.  A tick enqueues the set-up of newly admitted requests and one CG
+// iteration for every active request, waits once for all streams, launches the
+// true residual of converged requests, then preconditions every group (new
+// requests included) with one batched V-cycle whose smoother colour passes are
+// packed into one launch per (level, colour) across the group's requests
+// (levels may differ); converged requests are retired once their true residual,
+// queued ahead of the preconditioners, is done.  Each
 // request runs exactly the arithmetic of a stand-alone vps_pcg_solve with the
 // same deterministic kernels, so its result does not depend on the mix.
 #include <hip/hip_runtime.h>
