@@ -644,18 +644,29 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
 // coarse nodes of its cell with P[q][a] = phi_a(fine position q); a coarse vertex sums the
 // parts of its two cells (the fine node on the vertex lies in one run only, so every entry of
 // P1 is used once).  Fine boundary nodes count as 0; coarse boundary nodes are written 0.
-//  * restrict_plane_kernel: one workgroup per (fine plane, TX x TX coarse-column tile) reduces
-//    the plane along x0 and x1 (LDS) into T[zf][J1][J0] (nc x nc per fine plane);
-//  * restrict_z_kernel: one thread per coarse column (and chunk of cells) streams T along x2.
+//  * restrict_plane_kernel: one workgroup per (GP fine planes, TX x TX coarse-column tile)
+//    reduces the planes along x0 and x1 (LDS) into T[zf][J1][J0] (nc x nc per fine plane);
+//  * restrict_z_kernel: one thread per (coarse column, coarse cell along x2) combines T along x2.
 // Every launch is fully parallel (no chain of dependent planes inside a workgroup), the fine
-// vector is read once and the intermediate is a quarter of it.
+// vector is read once and the intermediate is a quarter of it.  Each thread issues all of its
+// global loads before it uses any of them, so a workgroup waits for memory once, not once per
+// element.
 
-template <int K>
+#ifndef VPS_RES_GP
+#define VPS_RES_GP 2
+#endif
+template <int K, typename T>
 struct ResPlane {
   static constexpr int CX = K == 1 ? 16 : K == 2 ? 8 : K == 3 ? 5 : K == 4 ? 4 : K == 5 ? 3 : 2;
   static constexpr int TX = K * CX;            // coarse columns per tile row
   static constexpr int NT = 256;
   static constexpr int IX = 2 * TX + 2 * K;    // fine extent [2o - 2K, 2o + 2TX - 1]
+  static constexpr int GP = sizeof(T) == 4 ? VPS_RES_GP : (VPS_RES_GP + 1) / 2;  // fine planes per workgroup
+  static constexpr int LPT = (IX * IX + NT - 1) / NT;       // loads per thread and plane
+  // LDS row strides: odd for the fine tile, 2 mod 4 for the x0-reduced tile, so that the lanes of
+  // a half-wave (consecutive rows) read different banks
+  static constexpr int XS = IX | 1;
+  static constexpr int RS = TX + (6 - TX % 4) % 4;
 };
 
 // in[t] = fine nodes 2K(C-1) + t, t < 4K (the runs of cells C-1 and C): coarse node a of cell C
@@ -678,42 +689,60 @@ __device__ __forceinline__ T restrict_run(const T* in, int a) {
 template <int K, typename T>
 __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict__ rf, T* __restrict__ tz,
                                                             long long nf, long long nc, int tiles) {
-  using S = ResPlane<K>;
-  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, RUN = 2 * K;
-  __shared__ T X[IX * IX];
-  __shared__ T Rx[IX * TX];
+  using S = ResPlane<K, T>;
+  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, RUN = 2 * K, GP = S::GP, LPT = S::LPT;
+  constexpr int XS = S::XS, RS = S::RS;
+  __shared__ T X[GP * IX * XS];
+  __shared__ T Rx[GP * IX * RS];
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = blk % tiles, ty = blk / tiles;
-  const long long zf = 1 + (long long)blockIdx.y;  // interior fine plane
+  const int z0 = 1 + GP * (int)blockIdx.y;  // first interior fine plane of the group
+  const int np = min(GP, (int)nf - 1 - z0);  // planes z0 .. z0 + np - 1 (<= nf - 2)
   const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;
-  const T* fz = rf + zf * nf * nf;
   const int tid = threadIdx.x;
-  // 32-bit plane offsets (the launcher checks nf^2 fits)
+  // 32-bit offsets from the group's first plane (the launcher checks GP nf^2 words fit)
   const int nfi = (int)nf, fy0 = (int)(2 * o1) - 2 * K, fx0 = (int)(2 * o0) - 2 * K;
-  for (int i = tid; i < IX * IX; i += NT) {
-    const int r = i / IX, c = i - r * IX;
-    const int fy = fy0 + r, fx = fx0 + c;
-    const bool ok = fy >= 1 && fy <= nfi - 2 && fx >= 1 && fx <= nfi - 2;
-    X[i] = ok ? ld_lane(fz, (unsigned)(fy * nfi + fx) * (unsigned)sizeof(T)) : T(0);
+  const T* fz = rf + (long long)z0 * nf * nf;
+  T v[GP][LPT];
+#pragma unroll
+  for (int j = 0; j < GP; ++j) {
+#pragma unroll
+    for (int l = 0; l < LPT; ++l) {
+      const int i = tid + l * NT;
+      const int r = i / IX, c = i - r * IX;
+      const int fy = fy0 + r, fx = fx0 + c;
+      const bool ok = j < np && i < IX * IX && fy >= 1 && fy <= nfi - 2 && fx >= 1 && fx <= nfi - 2;
+      v[j][l] = ok ? ld_lane(fz, (unsigned)((j * nfi + fy) * nfi + fx) * (unsigned)sizeof(T)) : T(0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < GP; ++j) {
+#pragma unroll
+    for (int l = 0; l < LPT; ++l) {
+      const int i = tid + l * NT;
+      const int r = i / IX, c = i - r * IX;
+      if (i < IX * IX) X[(j * IX + r) * XS + c] = v[j][l];
+    }
   }
   __syncthreads();
-  for (int task = tid; task < IX * CX; task += NT) {
-    using CT = gen::CellTables<T, K>;
-    const int r = task / CX, cx = task - r * CX;
+  for (int task = tid; task < GP * IX * CX; task += NT) {
+    const int j = task / (IX * CX), e = task - j * (IX * CX);
+    const int r = e / CX, cx = e - r * CX;
     T in[2 * RUN];
 #pragma unroll
-    for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * IX + RUN * cx + t];
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = X[(j * IX + r) * XS + RUN * cx + t];
 #pragma unroll
-    for (int a = 0; a < K; ++a) Rx[r * TX + cx * K + a] = restrict_run<K, T>(in, a);
+    for (int a = 0; a < K; ++a) Rx[(j * IX + r) * RS + cx * K + a] = restrict_run<K, T>(in, a);
   }
   __syncthreads();
-  T* out = tz + zf * nc * nc;
-  for (int task = tid; task < TX * CX; task += NT) {
-    using CT = gen::CellTables<T, K>;
-    const int cy = task / TX, c = task - cy * TX;
+  for (int task = tid; task < GP * TX * CX; task += NT) {
+    const int j = task / (TX * CX), e = task - j * (TX * CX);
+    if (j >= np) break;
+    const int cy = e / TX, c = e - cy * TX;
     T in[2 * RUN];
 #pragma unroll
-    for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(RUN * cy + t) * TX + c];
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(j * IX + RUN * cy + t) * RS + c];
+    T* out = tz + (long long)(z0 + j) * nc * nc;
     const long long gx = o0 + c;
 #pragma unroll
     for (int a = 0; a < K; ++a) {
@@ -723,56 +752,65 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   }
 }
 
-// Workgroup = 64 x 4 coarse columns (x0 fastest); blockIdx.z = a chunk of cz coarse cells along x2.
-// A thread walks its column through the chunk: each fine plane of a cell's run is read once and
-// adds P[q][a] times its value to the cell's k+1 coarse nodes; a cell's last node is carried to the
-// next cell's first.  The chunk's first vertex takes the run of the cell before the chunk (one run
-// of halo).  Sums run in the same order as the node-by-node definition (previous run, then own run).
+// Workgroup = 64 x 4 coarse columns (x0 fastest); blockIdx.z = the coarse cell C along x2.  A
+// thread loads the fine planes of the run before C (its contribution to C's first node) and of
+// C's own run, then adds P[q][a] times each to the cell's coarse nodes.  Sums run in the same
+// order as the node-by-node definition (previous run, then own run).
 template <int K, typename T>
 __global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc,
-                                                        int cz) {
+                                                        T* __restrict__ xz) {
   constexpr int NP = K + 1, RUN = 2 * K;
   using CT = gen::CellTables<T, K>;
   const int gx = blockIdx.x * 64 + threadIdx.x, gy = blockIdx.y * 4 + threadIdx.y;
   if (gx >= nc || gy >= nc) return;
   const int ncc = (nc - 1) / K;  // coarse cells along x2
-  const int C0 = blockIdx.z * cz, C1 = min(C0 + cz, ncc);
+  const int C = blockIdx.z;
   const long long nc2 = (long long)nc * nc;
   const unsigned off = (unsigned)(gy * nc + gx) * (unsigned)sizeof(T);  // within a plane
   const bool col = gx > 0 && gx < nc - 1 && gy > 0 && gy < nc - 1;     // else a boundary column: 0
-  T carry = T(0);  // the previous cell's contribution to the current cell's first node
-  if (C0 > 0) {
+  // planes outside [1, nf - 2] take no part; their loads read a clamped (valid) plane
+  T prev[RUN], own[RUN];
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-      const int zf = RUN * (C0 - 1) + q;
-      if (zf >= 1) carry = fma(CT::P[q * NP + K], ld_lane(tz + zf * nc2, off), carry);
-    }
+  for (int q = 0; q < RUN; ++q) {
+    const int zp = max(RUN * (C - 1) + q, 1), zo = min(max(RUN * C + q, 1), nf - 2);
+    prev[q] = ld_lane(tz + zp * nc2, off);
+    own[q] = ld_lane(tz + zo * nc2, off);
   }
-  for (int C = C0; C < C1; ++C) {
-    T s[NP];
-    s[0] = carry;
+  // all loads are in flight before the first use (the uses below are conditional, and a load
+  // sunk into its branch would wait for memory once per plane)
 #pragma unroll
-    for (int a = 1; a < NP; ++a) s[a] = T(0);
+  for (int q = 0; q < RUN; ++q) asm volatile("" : "+v"(prev[q]), "+v"(own[q])::"memory");
+  T carry = T(0);  // the previous cell's contribution to this cell's first node
+  if (C > 0) {
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-      const int zf = RUN * C + q;
-      if (zf >= 1 && zf <= nf - 2) {
-        const T v = ld_lane(tz + zf * nc2, off);
+    for (int q = 0; q < RUN; ++q)
+      if (RUN * (C - 1) + q >= 1) carry = fma(CT::P[q * NP + K], prev[q], carry);
+  }
+  T s[NP];
+  s[0] = carry;
 #pragma unroll
-        for (int a = 0; a < NP; ++a) {
-          if (q == 0 && a > 0) continue;  // the run's first fine node is the coarse vertex itself
-          s[a] = fma(CT::P[q * NP + a], v, s[a]);
-        }
+  for (int a = 1; a < NP; ++a) s[a] = T(0);
+#pragma unroll
+  for (int q = 0; q < RUN; ++q) {
+    const int zf = RUN * C + q;
+    if (zf >= 1 && zf <= nf - 2) {
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        if (q == 0 && a > 0) continue;  // the run's first fine node is the coarse vertex itself
+        s[a] = fma(CT::P[q * NP + a], own[q], s[a]);
       }
     }
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      const int zc = K * C + a;
-      st_lane(rc + zc * nc2, off, col && zc > 0 ? s[a] : T(0));
-    }
-    carry = s[K];
   }
-  if (C1 == ncc) st_lane(rc + (nc - 1) * nc2, off, T(0));  // the last coarse plane is a boundary plane
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    const int zc = K * C + a;
+    st_lane(rc + zc * nc2, off, col && zc > 0 ? s[a] : T(0));
+    if (xz) st_lane(xz + zc * nc2, off, T(0));
+  }
+  if (C == ncc - 1) {
+    st_lane(rc + (nc - 1) * nc2, off, T(0));  // the last coarse plane is a boundary plane
+    if (xz) st_lane(xz + (nc - 1) * nc2, off, T(0));
+  }
 }
 
 // ------------------------------------------------------- boundary and rhs
@@ -979,28 +1017,22 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
 // 3D: in-plane reduction of every fine plane, then the x2 reduction (scratch t: nf x nc x nc).
 // 2D: x0 pass into t (nf x nc), then the x1 pass.
 template <int D, int K, typename T>
-hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t) {
+hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t, void* xz) {
   const int nf = (int)fine.n1d, nc = (int)(K * (fine.ncells / 2) + 1);
   const int ncc = (nc - 1) / K;
   if (D == 3) {
-    using S = ResPlane<K>;
+    using S = ResPlane<K, T>;
     const int tiles = ceil_div(nc, S::TX);
-    if ((long long)tiles * tiles > 0x7fffffffLL || nf - 2 > 65535 ||
-        (long long)nf * nf * (long long)sizeof(T) >= (1LL << 31))
+    const int groups = ceil_div(nf - 2, S::GP);
+    if ((long long)tiles * tiles > 0x7fffffffLL || groups > 65535 ||
+        (long long)S::GP * nf * nf * (long long)sizeof(T) >= (1LL << 31))
       return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)(nf - 2)), dim3(S::NT),
+    hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)groups), dim3(S::NT),
                        0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
-    if (nc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32)) return hipErrorInvalidConfiguration;
-    // chunks of coarse cells along x2: about 2048 waves in all
-    const int ncc_z = (nc - 1) / K;
-    const long long cols = (long long)nc * nc;
-    int chunks = (int)((2048LL * 64 + cols - 1) / cols);
-    if (chunks > ncc_z) chunks = ncc_z;
-    if (chunks < 1) chunks = 1;
-    const int cz = (ncc_z + chunks - 1) / chunks;
-    chunks = (ncc_z + cz - 1) / cz;
-    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)chunks),
-                       dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, cz);
+    if (nc > 65535 || ncc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32))
+      return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)ncc),
+                       dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, (T*)xz);
   } else {
     // grid x: 256-thread blocks over one output plane (rows flattened)
     if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
@@ -1009,6 +1041,10 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
                        0, st, (const T*)rf, (T*)t, nf, nc, nf, 1);
     hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), dim3((unsigned)(((long long)nc * nc + 255) / 256)), dim3(256),
                        0, st, (const T*)t, (T*)rc, nf, nc, nc, nc, 1);
+    if (xz) {
+      hipError_t e = launch_fill(sizeof(T) == 8 ? 0 : 1, xz, (long long)nc * nc, 0.0, st);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }
@@ -1104,8 +1140,9 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
   VPS_DISPATCH(pro_launch, fine, prec, e, xf, st);
 }
 
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st) {
-  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t);
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st,
+                           void* xc_zero) {
+  VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t, xc_zero);
 }
 
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st) {

@@ -65,8 +65,10 @@ hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const vo
 hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
                               hipStream_t st, bool* fused);
 // Restriction P^T of a fine-level vector (fine boundary entries ignored, coarse boundary written 0);
-// t is scratch of restrict_scratch_elems(fine) elements.
-hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st);
+// t is scratch of restrict_scratch_elems(fine) elements.  A non-null xc_zero (a coarse-level vector)
+// is set to 0 as well, which saves the V-cycle a fill launch per level.
+hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st,
+                           void* xc_zero = nullptr);
 inline long long restrict_scratch_elems(int dim, int k, int fine_level) {
   const long long nf = (long long)k * (1LL << fine_level) + 1, nc = (long long)k * (1LL << (fine_level - 1)) + 1;
   return dim == 2 ? nf * nc : nf * nc * nc;

@@ -244,11 +244,11 @@ Status vcycle_top(Problem* p, int prec, int top, const void* bT, void* xT, bool 
   for (int lvl = top; lvl >= 2; --lvl) {
     const void* b = lvl == top ? bT : p->lv[lvl].b[prec];
     void* x = lvl == top ? xT : p->lv[lvl].x[prec];
-    if (lvl < top) VPS_HIP(launch_fill(prec, x, p->lv[lvl].N, 0.0, p->stream));
+    // below the top, x starts from 0: the restriction into this level zeroed it
     VPS_TRY(smoother(p, lvl, prec, vcycle_mode(p), false, b, x, lvl < top || top_zero));
     VPS_HIP(launch_operator(p->geom(lvl), prec, x, b, p->lv[lvl].r[prec], p->stream));
     VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t[prec],
-                            p->stream));
+                            p->stream, lvl - 1 >= 2 ? p->lv[lvl - 1].x[prec] : nullptr));
   }
   VPS_TRY(coarse_solve(p, prec, p->lv[1].b[prec], p->lv[1].x[prec]));
   // ascend
@@ -389,14 +389,14 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
     return Status::ok();
   };
   for (int lvl = Lmax; lvl >= 2; --lvl) {
-    for (int i = 0; i < n; ++i)
-      if (ps[i]->L > lvl) VPS_HIP(launch_fill(prec, level_x(i, lvl), ps[i]->lv[lvl].N, 0.0, st));
-    VPS_TRY(smooth(lvl, false, top_zero));  // levels below a member's top start from 0
+    // levels below a member's top start from 0 (the restriction into them zeroed x)
+    VPS_TRY(smooth(lvl, false, top_zero));
     for (int i = 0; i < n; ++i) {
       if (ps[i]->L < lvl) continue;
       Problem* p = ps[i];
       VPS_HIP(launch_operator(p->geom(lvl), prec, level_x(i, lvl), level_b(i, lvl), p->lv[lvl].r[prec], st));
-      VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t[prec], st));
+      VPS_HIP(launch_restrict(p->geom(lvl), prec, p->lv[lvl].r[prec], p->lv[lvl - 1].b[prec], p->lv[lvl].t[prec], st,
+                              lvl - 1 >= 2 ? p->lv[lvl - 1].x[prec] : nullptr));
     }
   }
   for (int i = 0; i < n; ++i) VPS_TRY(coarse_solve(ps[i], prec, level_b(i, 1), level_x(i, 1)));
