@@ -85,6 +85,8 @@ hipError_t launch_l2_error(const LevelGeom& g, const double* x, const double* V,
 // vector.hip
 int reduction_parts();  // partial slots the reductions use (pairs: 2x this many doubles)
 hipError_t launch_fill(int prec, void* x, long long n, double v, hipStream_t st);
+// dst = (double)src, zero = 0 (n entries each)
+hipError_t launch_widen_zero(const float* src, double* dst, double* zero, long long n, hipStream_t st);
 hipError_t launch_cast(int from_prec, const void* src, void* dst, long long n, hipStream_t st);
 hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, double* dst, double* partial,
                                      double* out, int* bad, hipStream_t st);

@@ -229,8 +229,7 @@ Status coarse_solve(Problem* p, int prec, const void* b, void* x) {
     return Status::ok();
   }
   if (!p->c64_b) return Status{-1, "FP32 coarse solve needs the FP32 hierarchy"};
-  VPS_HIP(launch_cast(1, b, p->c64_b, N, p->stream));
-  VPS_HIP(launch_fill(0, p->c64_x, N, 0.0, p->stream));
+  VPS_HIP(launch_widen_zero(static_cast<const float*>(b), p->c64_b, p->c64_x, N, p->stream));
   VPS_HIP(launch_colour_pass(g, 0, kModeMultiplicative, 0, p->c64_b, p->c64_x, p->stream));
   VPS_HIP(launch_cast(0, p->c64_x, x, N, p->stream));
   return Status::ok();

@@ -25,6 +25,16 @@ __global__ void cast_kernel(const S* __restrict__ src, D* __restrict__ dst, long
     dst[i] = (D)src[i];
 }
 
+// dst = (double)src and zero = 0 over the same range (the FP64 coarse solve of the FP32 V-cycle:
+// its right-hand side and starting iterate in one launch)
+__global__ void widen_zero_kernel(const float* __restrict__ src, double* __restrict__ dst, double* __restrict__ zero,
+                                  long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    dst[i] = (double)src[i];
+    zero[i] = 0.0;
+  }
+}
+
 // dst = src with boundary entries 0 (FP64), also returns partials of src.src on the interior
 // and a non-finite flag.
 __global__ void copy_interior_kernel(const double* __restrict__ src, double* __restrict__ dst, int dim, long long n1d,
@@ -172,6 +182,12 @@ hipError_t launch_cast(int from_prec, const void* src, void* dst, long long n, h
   else
     hipLaunchKernelGGL((cast_kernel<float, double>), dim3(grid_for(n)), dim3(256), 0, st, (const float*)src,
                        (double*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_zero(const float* src, double* dst, double* zero, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_zero_kernel, dim3(grid_for(n)), dim3(256), 0, st, src, dst, zero, n);
   return hipGetLastError();
 }
 
