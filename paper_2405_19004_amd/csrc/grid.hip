@@ -985,7 +985,7 @@ hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void
 }
 
 #ifndef VPS_OP_STREAM_MIN_CELLS
-#define VPS_OP_STREAM_MIN_CELLS 64
+#define VPS_OP_STREAM_MIN_CELLS 32
 #endif
 constexpr long long kOpStreamMinCells = VPS_OP_STREAM_MIN_CELLS;
 
