@@ -460,11 +460,15 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
     const int zl = task / TI, yl = task - zl * TI;
     const long long gz = D == 3 ? c2 + zl : 0, gy = c1 + yl;
     const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && (D == 2 || (gz < n1dc && !is_bnd(gz, n1dc)));
+    // every load of the row first, at indices clamped into the grid; out-of-range values taken as 0
+    const long long row = (D == 3 ? min(gz, n1dc - 1) * nc2 : 0) + min(gy, n1dc - 1) * n1dc;
     T in[TI];
+#pragma unroll
+    for (int j = 0; j < TI; ++j) in[j] = e[row + min(c0 + j, n1dc - 1)];
 #pragma unroll
     for (int j = 0; j < TI; ++j) {
       const long long gx = c0 + j;
-      in[j] = (ok && gx < n1dc && !is_bnd(gx, n1dc)) ? e[(D == 3 ? gz * nc2 : 0) + gy * n1dc + gx] : T(0);
+      if (!(ok && gx < n1dc && !is_bnd(gx, n1dc))) in[j] = T(0);
     }
 #pragma unroll
     for (int xo = 0; xo < TO; ++xo) {
