@@ -40,14 +40,17 @@ __global__ void widen_zero_kernel(const float* __restrict__ src, double* __restr
 }
 
 // dst = src with boundary entries 0 (FP64), also returns partials of src.src on the interior
-// and a non-finite flag.
-__global__ void copy_interior_kernel(const double* __restrict__ src, double* __restrict__ dst, int dim, long long n1d,
-                                     long long ntot, double* __restrict__ partial, int* __restrict__ bad) {
+// and a non-finite flag.  I = unsigned int when every index fits in 32 bits (the coordinates then
+// take 32-bit divisions), else long long.
+template <typename I>
+__global__ void copy_interior_kernel(const double* __restrict__ src, double* __restrict__ dst, int dim, long long n1d_,
+                                     long long ntot_, double* __restrict__ partial, int* __restrict__ bad) {
   __shared__ double red[kRedThreads];
   double acc = 0.0;
   int nonfinite = 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (long long)gridDim.x * blockDim.x) {
-    const long long i0 = i % n1d, r = i / n1d, i1 = r % n1d, i2 = r / n1d;
+  const I n1d = (I)n1d_, ntot = (I)ntot_;
+  for (I i = (I)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (I)gridDim.x * blockDim.x) {
+    const I i0 = i % n1d, r = i / n1d, i1 = r % n1d, i2 = r / n1d;
     bool bnd = i0 == 0 || i0 == n1d - 1 || i1 == 0 || i1 == n1d - 1 || (dim == 3 && (i2 == 0 || i2 == n1d - 1));
     double v = bnd ? 0.0 : src[i];
     if (!isfinite(v)) nonfinite = 1;
@@ -230,8 +233,13 @@ hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, 
                                      double* out, int* bad, hipStream_t st) {
   long long ntot = dim == 2 ? n1d * n1d : n1d * n1d * n1d;
   const int parts = reduction_parts();
-  hipLaunchKernelGGL(copy_interior_kernel, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot, partial,
-                     bad);
+  // 32-bit indices need ntot plus one grid stride to stay below 2^32
+  if (ntot + (long long)parts * kRedThreads < (1LL << 32))
+    hipLaunchKernelGGL(copy_interior_kernel<unsigned>, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot,
+                       partial, bad);
+  else
+    hipLaunchKernelGGL(copy_interior_kernel<long long>, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot,
+                       partial, bad);
   hipLaunchKernelGGL(finalize1_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
   return hipGetLastError();
 }
