@@ -107,3 +107,29 @@ def test_bad_requests_fail_alone():
         assert d2 and s2.status == 0
     finally:
         vps.vps_server_destroy(srv)
+
+
+def test_zero_rhs_request_finishes_at_admission():
+    # b = 0: the solve ends at its set-up (x = 0, no iteration); a request beside it is unaffected
+    b_ok = _rhs(3, 2, 3, 12)
+    b_zero = torch.zeros_like(b_ok)
+    x_ref, its_ref, st_ref = _alone(3, 2, 3, b_ok, vps.VPS_SOLVE_MIXED)
+    srv = vps.vps_server_create(1 << 30, 4)
+    try:
+        x0, x1 = torch.full_like(b_ok, 5.0), torch.full_like(b_ok, 5.0)
+        t0 = vps.vps_server_submit(srv, 3, 2, 3, b_zero.data_ptr(), x0.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        t1 = vps.vps_server_submit(srv, 3, 2, 3, b_ok.data_ptr(), x1.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        vps.vps_server_step(srv)
+        d0, s0 = vps.vps_server_poll(srv, t0)
+        assert d0 and s0.status == 0 and s0.iterations == 0 and s0.rel_residual == 0.0
+        for _ in range(200):
+            a, q = vps.vps_server_step(srv)
+            if a == 0 and q == 0:
+                break
+        d1, s1 = vps.vps_server_poll(srv, t1)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(x0).item() == 0
+        assert d1 and s1.status == st_ref and s1.iterations == its_ref
+        assert torch.equal(x1, x_ref)
+    finally:
+        vps.vps_server_destroy(srv)
