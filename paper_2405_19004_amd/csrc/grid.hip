@@ -650,7 +650,7 @@ __global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out
 // P1 is used once).  Fine boundary nodes count as 0; coarse boundary nodes are written 0.
 //  * restrict_plane_kernel: one workgroup per (GP fine planes, TX x TX coarse-column tile)
 //    reduces the planes along x0 and x1 (LDS) into T[zf][J1][J0] (nc x nc per fine plane);
-//  * restrict_z_kernel: one thread per (coarse column, coarse cell along x2) combines T along x2.
+//  * restrict_z_kernel: one thread per (coarse column, two coarse cells along x2) combines T along x2.
 // Every launch is fully parallel (no chain of dependent planes inside a workgroup), the fine
 // vector is read once and the intermediate is a quarter of it.  Each thread issues all of its
 // global loads before it uses any of them, so a workgroup waits for memory once, not once per
@@ -756,64 +756,69 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
   }
 }
 
-// Workgroup = 64 x 4 coarse columns (x0 fastest); blockIdx.z = the coarse cell C along x2.  A
-// thread loads the fine planes of the run before C (its contribution to C's first node) and of
-// C's own run, then adds P[q][a] times each to the cell's coarse nodes.  Sums run in the same
-// order as the node-by-node definition (previous run, then own run).
+// Workgroup = 64 x 4 coarse columns (x0 fastest); blockIdx.z = a pair of coarse cells along x2.  A
+// thread loads the fine planes of the run before its first cell and of its cells' own runs (each
+// run once), then for each cell C adds P[q][a] times each plane to the cell's coarse nodes.  Sums
+// run in the same order as the node-by-node definition (previous run, then own run).
+constexpr int kResCellsPerThread = 2;
 template <int K, typename T>
 __global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc,
                                                         T* __restrict__ xz) {
-  constexpr int NP = K + 1, RUN = 2 * K;
+  constexpr int NP = K + 1, RUN = 2 * K, CPT = kResCellsPerThread;
   using CT = gen::CellTables<T, K>;
   const int gx = blockIdx.x * 64 + threadIdx.x, gy = blockIdx.y * 4 + threadIdx.y;
   if (gx >= nc || gy >= nc) return;
   const int ncc = (nc - 1) / K;  // coarse cells along x2
-  const int C = blockIdx.z;
+  const int C0 = CPT * blockIdx.z;
   const long long nc2 = (long long)nc * nc;
   const unsigned off = (unsigned)(gy * nc + gx) * (unsigned)sizeof(T);  // within a plane
   const bool col = gx > 0 && gx < nc - 1 && gy > 0 && gy < nc - 1;     // else a boundary column: 0
-  // planes outside [1, nf - 2] take no part; their loads read a clamped (valid) plane
-  T prev[RUN], own[RUN];
+  // run[j] = fine planes of cell C0 - 1 + j; planes outside [1, nf - 2] take no part (their loads
+  // read a clamped, valid plane)
+  T run[CPT + 1][RUN];
 #pragma unroll
-  for (int q = 0; q < RUN; ++q) {
-    const int zp = max(RUN * (C - 1) + q, 1), zo = min(max(RUN * C + q, 1), nf - 2);
-    prev[q] = ld_lane(tz + zp * nc2, off);
-    own[q] = ld_lane(tz + zo * nc2, off);
-  }
-  // all loads are in flight before the first use (the uses below are conditional, and a load
-  // sunk into its branch would wait for memory once per plane)
+  for (int j = 0; j <= CPT; ++j) {
 #pragma unroll
-  for (int q = 0; q < RUN; ++q) asm volatile("" : "+v"(prev[q]), "+v"(own[q])::"memory");
-  T carry = T(0);  // the previous cell's contribution to this cell's first node
-  if (C > 0) {
-#pragma unroll
-    for (int q = 0; q < RUN; ++q)
-      if (RUN * (C - 1) + q >= 1) carry = fma(CT::P[q * NP + K], prev[q], carry);
-  }
-  T s[NP];
-  s[0] = carry;
-#pragma unroll
-  for (int a = 1; a < NP; ++a) s[a] = T(0);
-#pragma unroll
-  for (int q = 0; q < RUN; ++q) {
-    const int zf = RUN * C + q;
-    if (zf >= 1 && zf <= nf - 2) {
-#pragma unroll
-      for (int a = 0; a < NP; ++a) {
-        if (q == 0 && a > 0) continue;  // the run's first fine node is the coarse vertex itself
-        s[a] = fma(CT::P[q * NP + a], own[q], s[a]);
-      }
+    for (int q = 0; q < RUN; ++q) {
+      const int zf = min(max(RUN * (C0 - 1 + j) + q, 1), nf - 2);
+      run[j][q] = ld_lane(tz + zf * nc2, off);
     }
   }
 #pragma unroll
-  for (int a = 0; a < K; ++a) {
-    const int zc = K * C + a;
-    st_lane(rc + zc * nc2, off, col && zc > 0 ? s[a] : T(0));
-    if (xz) st_lane(xz + zc * nc2, off, T(0));
-  }
-  if (C == ncc - 1) {
-    st_lane(rc + (nc - 1) * nc2, off, T(0));  // the last coarse plane is a boundary plane
-    if (xz) st_lane(xz + (nc - 1) * nc2, off, T(0));
+  for (int c = 0; c < CPT; ++c) {
+    const int C = C0 + c;
+    if (C >= ncc) break;
+    T carry = T(0);  // the previous cell's contribution to this cell's first node
+    if (C > 0) {
+#pragma unroll
+      for (int q = 0; q < RUN; ++q)
+        if (RUN * (C - 1) + q >= 1) carry = fma(CT::P[q * NP + K], run[c][q], carry);
+    }
+    T s[NP];
+    s[0] = carry;
+#pragma unroll
+    for (int a = 1; a < NP; ++a) s[a] = T(0);
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+      const int zf = RUN * C + q;
+      if (zf >= 1 && zf <= nf - 2) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;  // the run's first fine node is the coarse vertex itself
+          s[a] = fma(CT::P[q * NP + a], run[c + 1][q], s[a]);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      const int zc = K * C + a;
+      st_lane(rc + zc * nc2, off, col && zc > 0 ? s[a] : T(0));
+      if (xz) st_lane(xz + zc * nc2, off, T(0));
+    }
+    if (C == ncc - 1) {
+      st_lane(rc + (nc - 1) * nc2, off, T(0));  // the last coarse plane is a boundary plane
+      if (xz) st_lane(xz + (nc - 1) * nc2, off, T(0));
+    }
   }
 }
 
@@ -1035,7 +1040,8 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
                        0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
     if (nc > 65535 || ncc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32))
       return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4), (unsigned)ncc),
+    hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4),
+                                                      (unsigned)ceil_div(ncc, kResCellsPerThread)),
                        dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, (T*)xz);
   } else {
     // grid x: 256-thread blocks over one output plane (rows flattened)
