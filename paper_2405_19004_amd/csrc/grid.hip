@@ -1031,7 +1031,9 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
   const int ncc = (nc - 1) / K;
   if (D == 3) {
     using S = ResPlane<K, T>;
-    const int tiles = ceil_div(nc, S::TX);
+    // tiles cover coarse columns 0 .. nc - 2: the x2 pass writes 0 on the last column and row
+    // whatever the plane values there are
+    const int tiles = ceil_div(nc - 1, S::TX);
     const int groups = ceil_div(nf - 2, S::GP);
     if ((long long)tiles * tiles > 0x7fffffffLL || groups > 65535 ||
         (long long)S::GP * nf * nf * (long long)sizeof(T) >= (1LL << 31))
