@@ -760,7 +760,10 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
 // thread loads the fine planes of the run before its first cell and of its cells' own runs (each
 // run once), then for each cell C adds P[q][a] times each plane to the cell's coarse nodes.  Sums
 // run in the same order as the node-by-node definition (previous run, then own run).
-constexpr int kResCellsPerThread = 2;
+#ifndef VPS_RES_CPT
+#define VPS_RES_CPT 2
+#endif
+constexpr int kResCellsPerThread = VPS_RES_CPT;
 template <int K, typename T>
 __global__ __launch_bounds__(256) void restrict_z_kernel(const T* __restrict__ tz, T* __restrict__ rc, int nf, int nc,
                                                         T* __restrict__ xz) {
