@@ -171,3 +171,55 @@ def patch_closure_ids(d, k, level, v):
 def patch_interior_ids(d, k, level, v):
     """Interior DoFs of the patch: (2k-1)^d nodes strictly inside the patch (Fig. 1 right)."""
     return box_ids(d, k, level, [k * (int(va) - 1) + 1 for va in v], 2 * k - 1)
+
+
+def patch_box_ids_many(d, k, level, verts, interior):
+    """Closure (interior=False) or interior (True) DoFs of many patches, one patch per row.
+
+    Row p lists the same nodes in the same order as patch_closure_ids / patch_interior_ids of
+    verts[p]."""
+    verts = np.asarray(verts, dtype=np.int64).reshape(-1, d)
+    n = n1d(k, level)
+    first = 1 if interior else 0
+    length = 2 * k - 1 if interior else 2 * k + 1
+    base = np.zeros(len(verts), dtype=np.int64)
+    for a in range(d):
+        base += (k * (verts[:, a] - 1) + first) * n ** a
+    return base[:, None] + box_ids(d, k, level, [0] * d, length)[None, :]
+
+
+def operator_rows(d, k, level, coords, x):
+    """(A x)_i for the nodes i at `coords` ((S, d) array of (c_0, ..., c_{d-1})), one row at a time.
+
+    `x` is any object indexable by flat node ids (a full-grid vector, or a device tensor).  A row
+    of A = sum_dir (x)_a (A1 or M1) couples node i only to the nodes whose coordinate differs by at
+    most k on every axis, so each row takes the (2k+1)^d box around i; Dirichlet nodes of x count
+    as 0 and Dirichlet rows are 0 (as in apply_operator).
+    """
+    n = n1d(k, level)
+    A1, M1 = global_1d_matrices(k, level)
+    A1, M1 = A1.toarray() if n <= 4097 else A1, M1.toarray() if n <= 4097 else M1
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, d)
+    out = np.zeros(len(coords))
+    for s, c in enumerate(coords):
+        if np.any(c == 0) or np.any(c == n - 1):
+            continue
+        lo = [max(int(c[a]) - k, 1) for a in range(d)]
+        hi = [min(int(c[a]) + k, n - 2) for a in range(d)]
+        ranges = [np.arange(lo[a], hi[a] + 1) for a in range(d)]
+        ids = np.zeros([len(r) for r in reversed(ranges)], dtype=np.int64)
+        for a in range(d):
+            shape = [1] * d
+            shape[d - 1 - a] = len(ranges[a])
+            ids = ids + ranges[a].reshape(shape) * n ** a
+        X = np.asarray(x[ids.reshape(-1)], dtype=np.float64).reshape(ids.shape)
+        total = 0.0
+        for direction in range(d):
+            T = X
+            for a in range(d):
+                row = (A1 if a == direction else M1)[int(c[a]), ranges[a]]
+                row = np.asarray(row.todense() if hasattr(row, "todense") else row).reshape(1, -1)
+                T = apply_1d(row, T, a, d)
+            total += float(np.asarray(T).reshape(-1)[0])
+        out[s] = total
+    return out

@@ -71,10 +71,16 @@ def fmg(d, k, L, b_levels, eps, maxit=50, post_reverse=False):
     return x, n
 
 
-def pcg(d, k, L, b, rtol, maxit=100, precondition=True):
+def pcg(d, k, L, b, rtol, maxit=100, precondition=True, flexible=False, post_reverse=True):
     """Preconditioned CG for A_L x = b from x0 = 0, one V-cycle as preconditioner.
 
     Stops when the recursively updated residual satisfies ||r||_2 <= rtol ||b||_2.
+    `post_reverse` picks the colour order of the V-cycle's post-smoothing (see vcycle).
+    With `flexible` the new direction takes the Polak-Ribiere coefficient
+    beta = r_{k+1}.(z_{k+1} - z_k) / (r_k.z_k), which keeps CG convergent when the
+    preconditioner is not a fixed symmetric operator (the literal colour order of Alg. 1, or
+    an FP32 V-cycle inside the FP64 iteration); for a symmetric preconditioner r_{k+1}.z_k
+    vanishes in exact arithmetic and the two coefficients agree.
     Returns (x, iterations, history of ||r||/||b||).
     """
     b = np.asarray(b, dtype=np.float64).copy()
@@ -85,7 +91,11 @@ def pcg(d, k, L, b, rtol, maxit=100, precondition=True):
     hist = [1.0]
     if bnorm == 0.0:
         return x, 0, hist
-    z = vcycle(d, k, L, r, np.zeros_like(r)) if precondition else r.copy()
+
+    def prec(v):
+        return vcycle(d, k, L, v, np.zeros_like(v), post_reverse) if precondition else v.copy()
+
+    z = prec(r)
     p = z.copy()
     rz = r @ z
     it = 0
@@ -98,8 +108,9 @@ def pcg(d, k, L, b, rtol, maxit=100, precondition=True):
         hist.append(np.linalg.norm(r) / bnorm)
         if hist[-1] <= rtol:
             break
-        z = vcycle(d, k, L, r, np.zeros_like(r)) if precondition else r.copy()
-        rz_new = r @ z
-        p = z + (rz_new / rz) * p
-        rz = rz_new
+        z_new = prec(r)
+        rz_new = r @ z_new
+        beta = (rz_new - r @ z) / rz if flexible else rz_new / rz
+        p = z_new + beta * p
+        z, rz = z_new, rz_new
     return x, it, hist

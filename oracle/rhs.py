@@ -121,3 +121,22 @@ def l2_error(d, k, level, x, kappas, ucoefs, nq=None):
         shape[d - 1 - a] = nc * nq
         W = W * ws.reshape(shape)
     return float(np.sqrt(np.sum(W * (U - X) ** 2)))
+
+
+def rhs_sine_modes_at(d, k, level, kappas, coefs, coords):
+    """Entries of rhs_sine_modes at the nodes `coords` ((S, d) array of (c_0, ..., c_{d-1})) only,
+    from the same 1D load vectors; 0 on Dirichlet nodes.  For meshes too large to hold b."""
+    n = mesh.n1d(k, level)
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, d)
+    cache = {}
+    out = np.zeros(len(coords))
+    for kap, c in zip(kappas, coefs):
+        t = np.full(len(coords), float(c))
+        for a in range(d):
+            key = int(kap[a])
+            if key not in cache:
+                cache[key] = load_vector_1d(k, level, key)
+            t = t * cache[key][coords[:, a]]
+        out += t
+    out[np.any((coords == 0) | (coords == n - 1), axis=1)] = 0.0
+    return out

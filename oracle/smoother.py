@@ -212,3 +212,22 @@ def patch_update_local(d, k, level, x_closure, b_interior):
     I = patch_interior_local(d, k)
     r = np.asarray(b_interior) - Abar @ np.asarray(x_closure)
     return np.asarray(x_closure)[I] + np.linalg.solve(Aj, r)
+
+
+def patch_update_local_many(d, k, level, x_closures, b_interiors):
+    """patch_update_local for many patches at once, one patch per row.
+
+    x_closures: (P, (2k+1)^d) closure values (Dirichlet nodes 0); b_interiors: (P, (2k-1)^d).
+    Returns the (P, (2k-1)^d) new interior values x^I + A_j^{-1}(b^I - Abar_j x_closure).
+    """
+    Abar, _ = patch_matrices(d, k, level)
+    I = patch_interior_local(d, k)
+    X = np.asarray(x_closures, dtype=np.float64)
+    r = np.asarray(b_interiors, dtype=np.float64) - X @ Abar.T
+    return X[:, I] + sla.lu_solve(_patch_lu(d, k, level), r.T).T
+
+
+def patch_solve_many(d, k, level, r_interiors):
+    """A_j^{-1} r for many patch-interior vectors r (one per row): the local solve of the additive
+    smoother (eq:local-solver), by the dense LU of the explicit patch matrix."""
+    return sla.lu_solve(_patch_lu(d, k, level), np.asarray(r_interiors, dtype=np.float64).T).T

@@ -115,24 +115,3 @@ def test_boundary_smoother_in_vcycle_and_solvers(d, k, L):
         assert rel(host(x1), host(x2)) <= 1e-8
     Pf.close()
     P.close()
-
-
-def test_full_size_3d_q4_boundary_pass_equals_fused():
-    """3D Q4, 64^3 cells: the Boundary pass equals the fused multiplicative pass (itself checked
-    against the oracle on sampled patches at this size), every colour, FP64 and FP32."""
-    d, k, L = 3, 4, 6
-    case("full size boundary vs fused", d, k, L)
-    P = vps.Problem(d, k, L, vps.VPS_FLAG_FP64_HIERARCHY | vps.VPS_FLAG_NO_SOLVER)
-    g = torch.Generator(device="cpu").manual_seed(47)
-    n = P.n()
-    for dt, tol in ((F64, 1e-12), (F32, 2e-6)):
-        b = torch.rand(n, generator=g, dtype=F64).to(device="cuda", dtype=dt)
-        x = torch.rand(n, generator=g, dtype=F64).to(device="cuda", dtype=dt)
-        for c in range(8):
-            x1, x2 = x.clone(), x.clone()
-            P.color_pass(b, x1, c, vps.VPS_MULTIPLICATIVE)
-            P.color_pass(b, x2, c, BND)
-            torch.cuda.synchronize()
-            e = float((x1.double() - x2.double()).norm() / x1.double().norm())
-            assert e <= tol, (dt, c, e)
-    P.close()

@@ -2,9 +2,9 @@
 
 Bars: FP64 results within 1e-12 relative (2-norm) of the oracle; FP32 kernels
 within 1e-5; mixed-precision CG solutions within 1e-8 of the FP64 solution.
-Sizes span several tiles/workgroups and ragged tails; full workload sizes are
-checked on sampled patches or through properties the oracle evaluates at any
-size (true residual, L2 error).
+Sizes span several tiles/workgroups and ragged tails.  The launch shapes of the
+workload sizes are compared element by element in test_gpu_fullsize.py, and the
+solvers at those sizes in test_gpu_solves.py.
 """
 import sys
 
@@ -195,7 +195,7 @@ def test_pcg_fp64_matches_oracle(d, k, L):
     x, st = P.pcg_solve(dev(b), rtol=1e-8)
     assert st.status == 0
     assert st.iterations == it_ref
-    assert rel(host(x), x_ref) <= 1e-10
+    assert rel(host(x), x_ref) <= 1e-12
     true = np.linalg.norm(b - mesh.apply_operator(d, k, L, host(x))) / np.linalg.norm(b)
     assert true <= 1.01e-8 and abs(true - st.true_rel_residual) <= 1e-3 * true
 
@@ -245,30 +245,6 @@ def test_pcg_error_paths():
 
 
 # ------------------------------------------------------------- workload sizes
-
-def test_full_size_3d_q4_colour_pass_sampled():
-    """3D Q4, 64^3 cells: one colour pass, 64 sampled patches recomputed one by one by the oracle."""
-    d, k, L = 3, 4, 6
-    case("C4 colour pass sampled", d, k, L)
-    P = problem(d, k, L)
-    b = synth.random_interior(d, k, L, 91)
-    x = synth.random_interior(d, k, L, 92)
-    rng = np.random.default_rng(93)
-    for c in (0, 5, 7):
-        xt = dev(x)
-        P.color_pass(dev(b), xt, c, vps.VPS_MULTIPLICATIVE)
-        got = host(xt)
-        verts = mesh.patches_of_colour(d, L, c)
-        touched = np.zeros(got.shape, dtype=bool)
-        for j in rng.choice(len(verts), 64, replace=False):
-            v = verts[j]
-            I = mesh.patch_interior_ids(d, k, L, v)
-            ref = smoother.patch_update_local(d, k, L, x[mesh.patch_closure_ids(d, k, L, v)], b[I])
-            assert rel(got[I], ref) <= 1e-12
-        for v in verts:
-            touched[mesh.patch_interior_ids(d, k, L, v)] = True
-        assert np.array_equal(got[~touched], x[~touched])
-
 
 def test_full_size_operator_3d_q4():
     d, k, L = 3, 4, 6
@@ -322,6 +298,7 @@ def test_full_size_mixed_vs_fp64(d, k, L, tol):
     x64, s64 = P.pcg_solve(bt, rtol=tol)
     x32, s32 = P.pcg_solve(bt, rtol=tol, mode=vps.VPS_SOLVE_MIXED)
     assert s64.status == 0 and s32.status == 0
+    assert s64.iterations == s32.iterations
     a, c = host(x64), host(x32)
     assert rel(c, a) <= 1e-8
     b = host(bt)

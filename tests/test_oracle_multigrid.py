@@ -103,3 +103,30 @@ def test_table7_q1_error_extrapolates(golden_dir):
     e = rhs.l2_error(d, k, L, x, kap, rhs.exact_solution_coefs(kap, co))
     predicted = e * (2 ** L / gold["cells_per_direction"]) ** 2
     assert abs(predicted / gold["l2_error"] - 1) < 0.02, predicted
+
+
+@pytest.mark.parametrize("d,k,L", [(2, 2, 4), (3, 2, 3)])
+def test_flexible_beta_equals_standard_for_the_symmetric_vcycle(d, k, L):
+    """With reversed post-smoothing the V-cycle is symmetric, r_{k+1}.z_k = 0, and the
+    Polak-Ribiere coefficient reduces to the Fletcher-Reeves one of plain PCG."""
+    b = rhs.rhs_sine_modes(d, k, L, *synth.fourier_modes(d, seed=1))
+    x0, it0, h0 = multigrid.pcg(d, k, L, b, 1e-10)
+    x1, it1, h1 = multigrid.pcg(d, k, L, b, 1e-10, flexible=True)
+    assert it0 == it1
+    assert np.linalg.norm(x1 - x0) <= 1e-9 * np.linalg.norm(x0)
+    assert np.allclose(h0, h1, rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("d,k,levels", [(2, 2, (3, 4, 5)), (3, 2, (2, 3, 4))])
+def test_flexible_pcg_literal_order_converges_flat_in_h(d, k, levels):
+    """Alg. 1 read literally (same colour order after the coarse correction) is not symmetric;
+    flexible CG converges with it, in iteration counts that do not grow with 1/h, and its
+    solution solves the discrete system."""
+    its = []
+    for L in levels:
+        b = rhs.rhs_sine_modes(d, k, L, *synth.manufactured_sine(d))
+        x, it, hist = multigrid.pcg(d, k, L, b, 1e-8, flexible=True, post_reverse=False)
+        its.append(it)
+        r = b - mesh.apply_operator(d, k, L, x)
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b)
+    assert max(its) - min(its) <= 1, its

@@ -78,3 +78,18 @@ def test_operator_spd(d, k, level):
     A = mesh.operator_matrix(d, k, level).toarray()
     assert np.allclose(A, A.T, atol=1e-14)
     sla.cholesky(A)
+
+
+@pytest.mark.parametrize("d,k,L", [(2, 1, 3), (2, 4, 2), (2, 7, 2), (3, 1, 2), (3, 3, 2), (3, 5, 1)])
+def test_operator_rows_equal_the_full_apply(d, k, L):
+    """Rows computed one at a time from the node's stencil box equal the axis-wise apply, including
+    rows next to and on the Dirichlet boundary (boundary values of x poisoned: never read)."""
+    import synth
+    x = synth.random_interior(d, k, L, 13)
+    ref = mesh.apply_operator(d, k, L, x)
+    xg = x.copy()
+    xg[mesh.boundary_mask(d, k, L)] = np.nan
+    n = mesh.n1d(k, L)
+    coords = np.array(list(np.ndindex(*([n] * d))))[:, ::-1]  # (c_0, ..., c_{d-1}) in flat order
+    got = mesh.operator_rows(d, k, L, coords, xg)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))

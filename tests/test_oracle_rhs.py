@@ -48,3 +48,13 @@ def test_random_interior_layout():
     bm = mesh.boundary_mask(2, 2, 4)
     assert v.shape == (33 * 33,)
     assert np.all(v[bm] == 0) and np.all(np.abs(v[~bm]) <= 1) and np.all(v[~bm] != 0)
+
+
+@pytest.mark.parametrize("d,k,L", [(2, 3, 3), (3, 2, 2), (3, 5, 1)])
+def test_rhs_entries_at_nodes_equal_the_full_vector(d, k, L):
+    import synth
+    kap, co = synth.fourier_modes(d, seed=4)
+    full = rhs.rhs_sine_modes(d, k, L, kap, co)
+    n = mesh.n1d(k, L)
+    coords = np.array(list(np.ndindex(*([n] * d))))[:, ::-1]
+    assert np.max(np.abs(rhs.rhs_sine_modes_at(d, k, L, kap, co, coords) - full)) <= 1e-15 * np.max(np.abs(full))
