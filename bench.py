@@ -31,13 +31,34 @@ RTOL = 1e-8
 PEAK_FP32 = 157.3e12  # MI355X published FP32 vector peak
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12  # MI355X HBM3E
-# LDS: 32 banks of 4 bytes per clock and compute unit, 256 compute units at 2.4 GHz
-PEAK_LDS = 32 * 4 * 256 * 2.4e9
+# LDS: bytes per clock and compute unit as assumed for CDNA3-class LDS (32 banks of 4 bytes); the
+# record states the figure next to the fraction
+LDS_BYTES_PER_CLK = 128
+PEAK_LDS = LDS_BYTES_PER_CLK * 256 * 2.4e9
 
 
-def colour_pass_flops(d, k):
-    """Algorithmic flops of one patch: interior-row residual by sum factorisation with reuse,
-    FD solve (S^T, eigenvalue scaling, S per direction) and update.  The 1D patch rows have
+def smoother_patch_flops(d, k):
+    """Algorithmic flops of one patch update (the measurement model of the smoother): the residual
+    on the patch-interior rows by sum factorisation with the partial products reused across
+    directions (Sec. 3.1.1), the fast-diagonalisation solve (S^T and S along every direction,
+    eq:inverse2d/3d, plus the eigenvalue scaling) and the update, every 1D matrix taken dense:
+      2D: 2 (2 n^2 m + 2 n m^2 + 4 m^3) + 2 m^2,
+      3D: 2 (2 n^3 m + 3 n^2 m^2 + 2 n m^3 + 6 m^4) + 2 m^3,   n = 2k+1, m = 2k-1."""
+    n, m = 2 * k + 1, 2 * k - 1
+    if d == 3:
+        return 2 * (2 * n ** 3 * m + 3 * n * n * m * m + 2 * n * m ** 3 + 6 * m ** 4) + 2 * m ** 3
+    return 2 * (2 * n * n * m + 2 * n * m * m + 4 * m ** 3) + 2 * m * m
+
+
+def smoother_patch_min_words(d, k):
+    """Minimum HBM words of one patch update: x on the closure skeleton and b on the interior read,
+    x on the interior written, (2k+1)^d + (2k-1)^d (each colour touches each node about once)."""
+    return (2 * k + 1) ** d + (2 * k - 1) ** d
+
+
+def colour_pass_issued_flops(d, k):
+    """Flops the colour-pass kernel executes per patch (smoother_patch_flops without the products
+    with structural zeros and with the eigenvector symmetry used).  The 1D patch rows have
     nnz = (2k-2)(k+1) + (2k+1) structural nonzeros (a cell-interior node couples to its cell's
     k+1 nodes, the middle vertex to all 2k+1); products with structural zeros are not counted.
     The eigenvectors are even or odd under the patch mirror, so one application of S or S^T to a
@@ -117,11 +138,12 @@ def progress(msg):
 def serving_run(v, n_requests, max_active=16, budget=64 << 30):
     """Continuous-batching server over a seeded stream of mixed (d, k, level) requests.
 
-    Right-hand sides are assembled on the device before the clock starts.  First
-    a closed-loop run (every request present at t = 0) measures capacity; then
-    the same requests arrive as a Poisson process at 80 % of that capacity and
-    latency (arrival -> completion) is recorded per request; last, a closed-loop
-    run of the same stream with plain FP64 solves gives the FP64 capacity.
+    Right-hand sides are assembled on the device before the clock starts.  First a closed-loop
+    run (every request present at t = 0) measures capacity; then the same requests arrive as a
+    Poisson process at 80 % of that capacity and latency (arrival -> completion) is recorded per
+    request.  The same arrival trace is replayed with plain FP64 solves, and one request at a time
+    (no batching, one slot); a closed-loop FP64 run gives the FP64 capacity.  Every request's
+    status and true residual are checked: a request that did not converge is counted as failed.
     """
     import synth
     trace = synth.serving_trace(seed=3, n_requests=n_requests, rate_per_s=1.0)
@@ -138,20 +160,24 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
         P.close()
     import torch
     torch.cuda.synchronize()
+    sizes = [r["n"] for r in trace]
+    classes = [(1e4, 1e5), (1e5, 1e6), (1e6, 1e7 + 1)]
 
-    def run(scale, mode=v.VPS_SOLVE_MIXED):
-        srv = v.vps_server_create(budget, max_active)
+    def run(scale, mode=v.VPS_SOLVE_MIXED, slots=max_active):
+        srv = v.vps_server_create(budget, slots)
         t0 = time.perf_counter()
-        pending = list(trace)
-        arrive, done = {}, {}
+        pending = list(range(len(trace)))
+        arrive, done, ticket_of = {}, {}, {}
         try:
             while True:
                 now = time.perf_counter() - t0
-                while pending and pending[0]["arrival"] * scale <= now:
-                    r = pending.pop(0)
+                while pending and trace[pending[0]]["arrival"] * scale <= now:
+                    i = pending.pop(0)
+                    r = trace[i]
                     t = v.vps_server_submit(srv, r["d"], r["k"], r["level"], r["b"].data_ptr(), r["x"].data_ptr(),
                                             RTOL, mode, 50)
                     arrive[t] = r["arrival"] * scale
+                    ticket_of[t] = i
                 active, queued = v.vps_server_step(srv)
                 now = time.perf_counter() - t0
                 for t in v.vps_server_completed(srv):
@@ -159,26 +185,51 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
                 if not pending and len(done) == len(trace):
                     break
                 if active == 0 and queued == 0 and pending:
-                    time.sleep(max(0.0, pending[0]["arrival"] * scale - (time.perf_counter() - t0)))
+                    time.sleep(max(0.0, trace[pending[0]]["arrival"] * scale - (time.perf_counter() - t0)))
             span = time.perf_counter() - t0
+            failed, worst = 0, 0.0
+            for t in done:
+                _, st = v.vps_server_poll(srv, t)
+                if st.status != 0 or not st.true_rel_residual <= 1.01 * RTOL:
+                    failed += 1
+                worst = max(worst, st.true_rel_residual)
         finally:
             v.vps_server_destroy(srv)
-        return span, sorted(done[t] - arrive[t] for t in done)
+        lat = {ticket_of[t]: done[t] - arrive[t] for t in done}
+        return span, lat, failed, worst
 
-    total = sum(r["n"] for r in trace)
-    span0, lat0 = run(0.0)
-    capacity = len(trace) / span0
+    def q(a, p):
+        a = sorted(a)
+        return a[min(len(a) - 1, int(round(p * (len(a) - 1))))] if a else None
+
+    def summary(span, lat, failed, worst):
+        vals = list(lat.values())
+        out = {"makespan_s": span, "dof_per_s": sum(sizes) / span, "req_per_s": len(trace) / span,
+               "p50_ms": 1e3 * q(vals, 0.5), "p99_ms": 1e3 * q(vals, 0.99), "mean_ms": 1e3 * sum(vals) / len(vals),
+               "failed": failed, "worst_true_rel_residual": worst, "by_size": {}}
+        for lo, hi in classes:
+            sel = [lat[i] for i in lat if lo <= sizes[i] < hi]
+            if sel:
+                out["by_size"]["%.0e-%.0e" % (lo, min(hi, 1e7))] = {
+                    "requests": len(sel), "p50_ms": 1e3 * q(sel, 0.5), "p99_ms": 1e3 * q(sel, 0.99)}
+        return out
+
+    total = sum(sizes)
+    closed = run(0.0)
+    capacity = len(trace) / closed[0]
     rate = 0.8 * capacity
-    span1, lat1 = run(1.0 / rate)
-    span64, lat64 = run(0.0, v.VPS_SOLVE_FP64)  # the same stream, plain FP64 solves, closed loop
-    q = lambda a, p: a[min(len(a) - 1, int(round(p * (len(a) - 1))))]
-    return {"requests": len(trace), "total_dofs": total, "closed_loop_req_per_s": capacity,
-            "closed_loop_dof_per_s": total / span0, "closed_loop_p50_ms": 1e3 * q(lat0, 0.5),
-            "closed_loop_p99_ms": 1e3 * q(lat0, 0.99), "arrival_rate_per_s": rate,
-            "p50_ms": 1e3 * q(lat1, 0.5), "p99_ms": 1e3 * q(lat1, 0.99), "mean_ms": 1e3 * sum(lat1) / len(lat1),
-            "dof_per_s": total / span1, "max_active": max_active,
-            "fp64_closed_loop_req_per_s": len(trace) / span64, "fp64_closed_loop_dof_per_s": total / span64,
-            "mixed_vs_fp64_closed_loop_speedup": span64 / span0}
+    res = {"requests": len(trace), "total_dofs": total, "max_active": max_active, "arrival_rate_per_s": rate}
+    res["closed_loop_mixed"] = summary(*closed)
+    res["poisson_mixed"] = summary(*run(1.0 / rate))
+    res["poisson_fp64"] = summary(*run(1.0 / rate, v.VPS_SOLVE_FP64))
+    res["poisson_mixed_one_at_a_time"] = summary(*run(1.0 / rate, v.VPS_SOLVE_MIXED, 1))
+    res["closed_loop_fp64"] = summary(*run(0.0, v.VPS_SOLVE_FP64))
+    res["mixed_vs_fp64_closed_loop_speedup"] = res["closed_loop_fp64"]["makespan_s"] / closed[0]
+    # headline figures of the Poisson replay at 80 % of the mixed capacity
+    res["p50_ms"], res["p99_ms"] = res["poisson_mixed"]["p50_ms"], res["poisson_mixed"]["p99_ms"]
+    res["dof_per_s"] = res["poisson_mixed"]["dof_per_s"]
+    res["failed"] = sum(res[k]["failed"] for k in res if isinstance(res[k], dict) and "failed" in res[k])
+    return res
 
 
 # Table 7 (3D, manufactured solution prod sin(pi x_i), residual reduction 1e-9): degree,
@@ -263,37 +314,64 @@ def variants_run(v, torch, P, b, stream):
     return res
 
 
-def cpu_baseline(N, vcycles_per_solve):
+def cpu_info():
+    """CPU model and the threads the oracle's BLAS runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = None
+    try:
+        import threadpoolctl
+        threads = max((p["num_threads"] for p in threadpoolctl.threadpool_info()), default=None)
+    except Exception:
+        pass
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return model, threads, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(N, vcycles_per_solve, reps=3):
     """The FP64 oracle (NumPy/SciPy) on a bounded sample of the same workload.
 
-    Sample: one multiplicative smoothing step (8 colour passes: global residual
-    + dense-LU patch solves) on the 64^3 Q4 level.  A solve performs two such
-    steps per V-cycle on that level; coarser levels, transfers and the CG
-    vector work are not counted, so the scaled figure is an upper bound for the
-    oracle's solve throughput.
+    Sample: one full oracle V-cycle (Alg. 1 with the bench's colour order: smoothing steps of
+    global residuals and dense-LU patch solves on every level, operator, transfers, dense coarse
+    solve) on 3D Q4 64^3, best of `reps`.  A solve applies one V-cycle per CG iteration plus the
+    initial one; the CG operator applications and vector updates are not counted, so the scaled
+    figure is an upper bound for the oracle's solve throughput.
     """
     import numpy as np
     import synth
-    from oracle import mesh, rhs, smoother
+    from oracle import mesh, multigrid, rhs, smoother, transfer
     kap, co = synth.fourier_modes(D, seed=1)
     b = rhs.rhs_sine_modes(D, K, L, kap, co)
-    x = np.zeros_like(b)
-    # oracle set-up (patch factorisation, index maps, 1D matrices) before the clock
-    mesh.global_1d_matrices(K, L)
-    mesh.boundary_mask(D, K, L)
-    smoother._patch_lu(D, K, L)
-    for c in range(2 ** D):
-        smoother._colour_index_arrays(D, K, L, c)
-    t0 = time.perf_counter()
-    smoother.multiplicative(D, K, L, b, x)
-    t = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    steps = 2 * vcycles_per_solve
-    return {"value": N / (t * steps), "unit": "DoF/s", "cores": threads, "kind": "oracle",
-            "sample": "one FP64 oracle smoothing step on 3D Q4 64^3 (%.1f s), scaled to the %d finest-level "
-                      "smoothing steps of one solve (upper bound: coarser levels and CG work not counted)"
-                      % (t, steps),
-            "smoothing_step_s": t}
+    # oracle set-up (patch factorisations, index maps, 1D matrices) before the clock
+    for lev in range(2, L + 1):
+        mesh.global_1d_matrices(K, lev)
+        mesh.boundary_mask(D, K, lev)
+        smoother._patch_lu(D, K, lev)
+        for c in range(2 ** D):
+            smoother._colour_index_arrays(D, K, lev, c)
+    multigrid.coarse_solve(D, K, np.zeros(mesh.n1d(K, 1) ** D))
+    transfer.restrict(D, K, 2, np.zeros(mesh.n1d(K, 2) ** D))
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        multigrid.vcycle(D, K, L, b, np.zeros_like(b), post_reverse=False)
+        times.append(time.perf_counter() - t0)
+    t = min(times)
+    model, threads, affinity = cpu_info()
+    return {"value": N / (t * vcycles_per_solve), "unit": "DoF/s", "cores": threads, "kind": "oracle",
+            "sample": "one FP64 oracle V-cycle on 3D Q4 64^3 (best of %d: %.1f s), scaled to the %d V-cycles of "
+                      "one solve (upper bound: the CG operator and vector work is not counted)"
+                      % (reps, t, vcycles_per_solve),
+            "vcycle_s": times, "cpu_model": model, "cpus_available": affinity,
+            "note": "a plain correctness oracle, not a tuned CPU solver"}
 
 
 def main():
@@ -393,15 +471,18 @@ def main():
     out["smoother_variants"] = variants_run(v, torch, P, b, stream)
     out["fmg"] = fmg_run(v, torch, P, kap, co)
 
-    # roofline of the dominant kernel: the FP32 colour pass on the finest level
+    # roofline of the dominant kernel: the FP32 colour pass on the finest level.  Algorithmic work
+    # per patch is the measurement model's (smoother_patch_flops / smoother_patch_min_words); the
+    # binding roof is the one with the longer time at peak.
     info = P.info()
     bb = b.to(torch.float32)
     xx = torch.zeros_like(bb)
     launches = 8 * 10
     t_all = event_time(lambda: [P.color_pass(bb, xx, c) for c in range(8)], stream, 10) / 8
     patches = sum(info.color_count[c] for c in range(8)) / 8
-    flops = colour_pass_flops(D, K) * patches
-    bytes_ = colour_pass_bytes(D, K, 4) * patches
+    flops = smoother_patch_flops(D, K) * patches
+    bytes_ = 4 * smoother_patch_min_words(D, K) * patches
+    issued = colour_pass_issued_flops(D, K) * patches
     lds_bytes = colour_pass_lds_bytes_3d(K, 4, 2) * patches
     traffic = None
     tf = os.path.join(ROOT, "profiles", "colour_pass_3d_q4_fp32_traffic.json")
@@ -409,27 +490,34 @@ def main():
         rec = json.load(open(tf))
         if rec.get("source_hash") == smoother_source_hash():  # counters describe this exact kernel source
             traffic = rec.get("bytes_per_launch")
-    # the binding roof is the one with the longer time at peak: HBM (algorithmic bytes / 8 TB/s) or
-    # the vector ALU (algorithmic flops / 157.3 TFLOP/s)
     t_hbm, t_alu = bytes_ / PEAK_HBM, flops / PEAK_FP32
     common = {"kernel": "colour_pass_kernel<3,4,float,multiplicative,2 patches per workgroup>",
-              "avg_launch_us": 1e6 * t_all, "algorithmic_bytes_per_launch": bytes_, "flops_per_launch": flops,
-              "launches_timed": launches, "traffic": traffic,
+              "avg_launch_us": 1e6 * t_all, "patches_per_launch": patches,
+              "algorithmic_flops_per_patch": smoother_patch_flops(D, K),
+              "algorithmic_words_per_patch": smoother_patch_min_words(D, K),
+              "algorithmic_bytes_per_launch": bytes_, "algorithmic_flops_per_launch": flops,
+              "launches_timed": launches,
               "alu": {"achieved_tflops": flops / t_all / 1e12, "peak_tflops": PEAK_FP32 / 1e12,
-                      "frac": flops / t_all / PEAK_FP32},
+                      "frac": flops / t_all / PEAK_FP32,
+                      # the 157.3 TFLOP/s peak needs packed FP32 instructions, which this build does
+                      # not emit; one FP32 FMA per lane and clock gives half of it
+                      "peak_tflops_unpacked": PEAK_FP32 / 2e12, "frac_unpacked": 2 * flops / t_all / PEAK_FP32},
               "hbm": {"achieved_gbps": bytes_ / t_all / 1e9, "peak_gbps": PEAK_HBM / 1e9,
                       "frac": bytes_ / t_all / PEAK_HBM},
+              "executed": {"flops_per_launch": issued, "tflops": issued / t_all / 1e12,
+                           "note": "structural zeros of the 1D patch matrices skipped, eigenvector symmetry used"},
               "lds": {"achieved_tbps": lds_bytes / t_all / 1e12, "peak_tbps": PEAK_LDS / 1e12,
-                      "frac": lds_bytes / t_all / PEAK_LDS, "bytes_per_launch": lds_bytes}}
+                      "frac": lds_bytes / t_all / PEAK_LDS, "bytes_per_launch": lds_bytes,
+                      "bytes_per_clock_per_cu": LDS_BYTES_PER_CLK}}
     if t_hbm >= t_alu:
         out["roofline"] = dict(bound="hbm", achieved=bytes_ / t_all / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                               frac=bytes_ / t_all / PEAK_HBM, **common)
+                               frac=bytes_ / t_all / PEAK_HBM, traffic=traffic, **common)
     else:
         out["roofline"] = dict(bound="alu", achieved=flops / t_all / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                               frac=flops / t_all / PEAK_FP32, **common)
+                               frac=flops / t_all / PEAK_FP32, traffic=traffic, **common)
     xz = torch.zeros_like(b)
     t64 = event_time(lambda: [P.color_pass(b, xz, c) for c in range(8)], stream, 5) / 8
-    bytes64 = colour_pass_bytes(D, K, 8) * patches
+    bytes64 = 8 * smoother_patch_min_words(D, K) * patches
     out["roofline_fp64_colour_pass"] = {"bound": "hbm" if bytes64 / PEAK_HBM >= flops / PEAK_FP64 else "alu",
                                         "avg_launch_us": 1e6 * t64,
                                         "hbm_gbps": bytes64 / t64 / 1e9, "hbm_frac": bytes64 / t64 / PEAK_HBM,

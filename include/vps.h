@@ -221,17 +221,26 @@ int vps_host_table(int k, int which, double* out, int cap, int* n);
  * level) and reused by later requests. */
 typedef struct vps_server vps_server;
 
-/* hbm_budget_bytes: device bytes the server may hold; max_active: concurrent requests. */
+/* hbm_budget_bytes: device bytes the server may hold; max_active: concurrent requests.
+ * hip_stream: the caller's stream (NULL: the null stream).  Each submit marks it, and the
+ * request's first device work waits for that mark, so inputs written on this stream before
+ * the submit are seen complete.  The server's own work runs on private streams. */
 int vps_server_create(size_t hbm_budget_bytes, int max_active, void* hip_stream, vps_server** out);
 
 /* Queue a request.  b_dev: FP64 rhs (device, N values, caller keeps it alive until done);
- * x_dev: FP64 output (device).  *ticket receives the request id.  VPS_EBUSY if its
- * footprint exceeds the whole budget. */
+ * x_dev: FP64 output (device), valid once poll reports the request done (the server has then
+ * waited for its last kernel; the caller must not touch x_dev before).  *ticket receives the
+ * request id.  VPS_EBUSY if its footprint exceeds the whole budget; VPS_EHIP if the caller's
+ * stream cannot be marked. */
 int vps_server_submit(vps_server* s, int dim, int degree, int level, const double* b_dev, double* x_dev,
                       double rtol, int solve_mode, int maxit, long long* ticket);
 
 /* One scheduler tick (admit, one CG iteration for every active request, retire). *n_active,
- * *n_queued (may be NULL) receive the counts after the tick.  Synchronises. */
+ * *n_queued (may be NULL) receive the counts after the tick.  Synchronises.  A request whose
+ * launches fail finishes with the error code as its status (see poll) and returns its
+ * hierarchy; the tick still returns VPS_OK and the server stays usable.  VPS_EHIP is returned
+ * only when waiting on the device fails: every request in flight then ends with that status
+ * and queued requests stay queued. */
 int vps_server_step(vps_server* s, int* n_active, int* n_queued);
 
 /* *done = 1 when the request finished (then *stats holds its result).  Host-only. */
@@ -247,6 +256,13 @@ int vps_server_completed(vps_server* s, long long* tickets, int cap, int* n);
 int vps_server_memory(vps_server* s, size_t* in_use, size_t* cached);
 
 int vps_server_destroy(vps_server* s);
+
+/* Testing hook for the failure paths of vps_server_step: the request `ticket` (not yet done)
+ * has its next launch at `stage` (0: admission, 1: CG iteration, 2: preconditioner, which
+ * ends its whole request group) report VPS_EHIP instead of running.  For callers that test
+ * error handling without a faulty device; has no other effect.  VPS_EINVAL on an unknown or
+ * finished ticket or a bad stage. */
+int vps_server_inject_fault(vps_server* s, long long ticket, int stage);
 
 #ifdef __cplusplus
 }

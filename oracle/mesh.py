@@ -188,8 +188,14 @@ def patch_box_ids_many(d, k, level, verts, interior):
     return base[:, None] + box_ids(d, k, level, [0] * d, length)[None, :]
 
 
-def operator_rows(d, k, level, coords, x):
+def operator_rows(d, k, level, coords, x, absolute=False):
     """(A x)_i for the nodes i at `coords` ((S, d) array of (c_0, ..., c_{d-1})), one row at a time.
+
+    absolute=True returns instead sum_dir ((x)_a |A1 or M1|) |x| on those rows: the sum of the
+    magnitudes of all products that make up (A x)_i in the Kronecker-sum form.  A computed row
+    sum differs from the exact one by at most gamma_n times this (the standard bound for
+    floating-point sums of products, with n the depth of the summation), which is what
+    tolerances on computed rows are measured against.
 
     `x` is any object indexable by flat node ids (a full-grid vector, or a device tensor).  A row
     of A = sum_dir (x)_a (A1 or M1) couples node i only to the nodes whose coordinate differs by at
@@ -199,6 +205,8 @@ def operator_rows(d, k, level, coords, x):
     n = n1d(k, level)
     A1, M1 = global_1d_matrices(k, level)
     A1, M1 = A1.toarray() if n <= 4097 else A1, M1.toarray() if n <= 4097 else M1
+    if absolute:
+        A1, M1 = abs(A1), abs(M1)
     coords = np.asarray(coords, dtype=np.int64).reshape(-1, d)
     out = np.zeros(len(coords))
     for s, c in enumerate(coords):
@@ -213,6 +221,8 @@ def operator_rows(d, k, level, coords, x):
             shape[d - 1 - a] = len(ranges[a])
             ids = ids + ranges[a].reshape(shape) * n ** a
         X = np.asarray(x[ids.reshape(-1)], dtype=np.float64).reshape(ids.shape)
+        if absolute:
+            X = np.abs(X)
         total = 0.0
         for direction in range(d):
             T = X

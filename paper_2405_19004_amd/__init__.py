@@ -76,6 +76,7 @@ _SIGS = {
     "vps_server_completed": (_I, [_P, ctypes.POINTER(_LL), _I, ctypes.POINTER(_I)]),
     "vps_server_memory": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "vps_server_destroy": (_I, [_P]),
+    "vps_server_inject_fault": (_I, [_P, _LL, _I]),
 }
 
 _lib = None
@@ -231,6 +232,11 @@ def vps_host_table(k, which):
 
 
 def vps_server_create(budget_bytes, max_active, hip_stream=None):
+    """hip_stream: the caller's stream as an integer handle; default torch's current stream."""
+    if hip_stream is None:
+        import torch
+        if torch.cuda.is_available():
+            hip_stream = torch.cuda.current_stream().cuda_stream
     h = _P()
     _call("vps_server_create", budget_bytes, max_active, hip_stream, ctypes.byref(h))
     return h
@@ -275,6 +281,10 @@ def vps_server_memory(s):
 
 def vps_server_destroy(s):
     return _call("vps_server_destroy", s)
+
+
+def vps_server_inject_fault(s, ticket, stage):
+    return _call("vps_server_inject_fault", s, ticket, stage)
 
 
 # ------------------------------------------------------------ torch layer

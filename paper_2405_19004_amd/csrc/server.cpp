@@ -1,7 +1,9 @@
 // Continuous-batching solve server (one GPU).
 //
-// Requests arrive with (dim, degree, level, rhs, tolerance, solve mode).  A
-// request is admitted, in arrival order, as soon as a slot is free and its
+// Requests arrive with (dim, degree, level, rhs, tolerance, solve mode).  The
+// caller's stream (given at creation) is marked at submit, and the request's
+// first device work waits for that mark, so a rhs written on the caller's
+// stream just before submit is read complete.  A request is admitted, in arrival order, as soon as a slot is free and its
 // device footprint fits the remaining memory budget; idle hierarchies of
 // finished requests are cached per (dim, degree, level, mode) and handed to
 // later requests of the same shape, and evicted (least recently used first)
@@ -16,6 +18,11 @@
 // queued ahead of the preconditioners, is done.  Each
 // request runs exactly the arithmetic of a stand-alone vps_pcg_solve with the
 // same deterministic kernels, so its result does not depend on the mix.
+//
+// A request whose launches fail ends with that error in its status and gives
+// its hierarchy back; the other requests and the server's accounting carry on.
+// Only a failed wait on a group stream (the device itself is in error) ends
+// every active request of the tick.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,9 +59,14 @@ struct Request {
   size_t bytes = 0;
   Slot slot;
   vps::CgState cs;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit
+  int inject = -1;             // test hook: the stage whose launch is made to fail
   bool admitted = false, done = false;
   vps_solve_stats_t stats{};
 };
+
+// Stages at which vps_server_inject_fault can make a request's launch fail.
+enum { kStageAdmit = 0, kStageIterate = 1, kStagePrecondition = 2 };
 
 unsigned flags_for(int mode) {
   return mode == VPS_SOLVE_MIXED ? VPS_FLAG_FP32_HIERARCHY : VPS_FLAG_FP64_HIERARCHY;
@@ -143,6 +155,7 @@ class LaunchPool {
 }  // namespace
 
 struct vps_server {
+  hipStream_t caller = nullptr;  // the caller's stream: request inputs are ready on it at submit
   size_t budget = 0;
   int max_active = 1;
   long long next_id = 1;
@@ -195,6 +208,9 @@ int acquire(vps_server* S, Request* r) {
       return 1;
     }
   }
+  // evict (least recently used first) only if that can make room: otherwise the request waits for
+  // active requests to finish and the cache stays
+  if (S->in_use + r->bytes > S->budget) return 0;
   while (S->in_use + S->cached + r->bytes > S->budget && !S->idle.empty()) {
     Slot victim = S->idle.back();
     S->idle.pop_back();
@@ -230,14 +246,36 @@ void finish(vps_server* S, Request* r) {
   r->stats.status = r->cs.stats.status;
 }
 
+void drop_ready(Request* r) {
+  if (r->ready) (void)hipEventDestroy(r->ready);
+  r->ready = nullptr;
+}
+
+// End request r with error `code` (its status) and give its hierarchy back to the cache: the
+// hierarchy holds no state a later request relies on (every solve starts by filling its vectors).
+void fail_request(vps_server* S, Request* r, int code, const std::string& msg) {
+  vps::set_last_error(msg);
+  r->cs.done = true;
+  r->cs.stats.status = code;
+  drop_ready(r);
+  finish(S, r);
+  if (r->slot.prob) release(S, r);
+}
+
+// The test hook: a launch of request r at `stage` reports an error instead of running.
+vps::Status injected(const Request* r, int stage) {
+  if (r->inject == stage) return vps::Status{VPS_EHIP, "fault injected by vps_server_inject_fault"};
+  return vps::Status::ok();
+}
+
 }  // namespace
 
 extern "C" {
 
 int vps_server_create(size_t hbm_budget_bytes, int max_active, void* hip_stream, vps_server** out) {
-  (void)hip_stream;
   if (!out || max_active < 1 || hbm_budget_bytes == 0) return sfail(VPS_EINVAL, "bad server arguments");
   vps_server* s = new vps_server();
+  s->caller = static_cast<hipStream_t>(hip_stream);
   s->budget = hbm_budget_bytes;
   s->max_active = max_active;
   const unsigned hw = std::thread::hardware_concurrency();
@@ -258,7 +296,19 @@ int vps_server_submit(vps_server* s, int dim, int degree, int level, const doubl
   size_t bytes = 0;
   if (int e = vps_footprint_bytes(dim, degree, level, flags_for(solve_mode), &bytes)) return sfail(e, vps_last_error());
   if (bytes > s->budget) return sfail(VPS_EBUSY, "request footprint exceeds the server memory budget");
+  // mark the caller's stream: the request's first device work waits for what is queued there now
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return sfail(VPS_EHIP, "hipEventCreate failed");
+  }
+  if (hipEventRecord(ready, s->caller) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(ready);
+    return sfail(VPS_EHIP, "hipEventRecord on the caller's stream failed");
+  }
   Request* r = new Request();
+  r->ready = ready;
   r->id = s->next_id++;
   r->dim = dim;
   r->k = degree;
@@ -279,69 +329,101 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
   if (!s) return sfail(VPS_EINVAL, "null server");
   using Key = std::tuple<int, int, int>;
   auto key_of = [](const Request* r) { return std::make_tuple(r->dim, r->k, r->mode); };
-  // Run fn(request) for each list of `lists` on the launch pool (one list per stream).
-  auto on_pool = [&](std::vector<std::vector<Request*>*>& lists, const std::function<vps::Status(Request*)>& fn) {
-    std::vector<vps::Status> res(lists.size());
+  // Run fn(request) for each list of `lists` on the launch pool (one list per stream); a request
+  // whose fn fails is recorded in `failed` (the others of its list still run).
+  using Failure = std::pair<Request*, vps::Status>;
+  auto on_pool = [&](std::vector<std::vector<Request*>*>& lists, const std::function<vps::Status(Request*)>& fn,
+                     std::vector<Failure>* failed) {
+    std::vector<std::vector<Failure>> res(lists.size());
     s->pool->run((int)lists.size(), [&](int i) {
       for (Request* r : *lists[i]) {
-        res[i] = fn(r);
-        if (res[i].code) return;
+        vps::Status st = fn(r);
+        if (st.code) res[i].push_back(Failure(r, st));
       }
     });
-    for (const vps::Status& st : res)
-      if (st.code) return st;
-    return vps::Status::ok();
+    for (auto& v : res) failed->insert(failed->end(), v.begin(), v.end());
   };
   // admit in arrival order; the rhs check of a new request waits for this tick's synchronisation
   std::vector<Request*> begun;
   while (!s->queue.empty() && (int)(s->active.size() + begun.size()) < s->max_active) {
     Request* r = s->queue.front();
     int got = acquire(s, r);
-    if (got < 0) return got;
     if (got == 0) break;
     s->queue.pop_front();
     r->admitted = true;
-    vps::Status st = vps::pcg_begin_launch(r->slot.prob, r->mode, r->b, r->x, &r->cs);
-    if (st.code) return sfail(st.code, st.msg);
+    if (got < 0) {
+      fail_request(s, r, got, vps_last_error());
+      continue;
+    }
+    vps::Status st = injected(r, kStageAdmit);
+    if (!st.code && hipStreamWaitEvent(r->slot.stream, r->ready, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      st = vps::Status{VPS_EHIP, "hipStreamWaitEvent on the submit mark failed"};
+    }
+    if (!st.code) st = vps::pcg_begin_launch(r->slot.prob, r->mode, r->b, r->x, &r->cs);
+    if (st.code) {
+      fail_request(s, r, st.code, st.msg);
+      continue;
+    }
+    drop_ready(r);  // released once the wait queued above has passed
     begun.push_back(r);
   }
   // one CG iteration for every active request (groups overlap on their streams; each group's
   // launches are issued by one host thread)
+  std::set<Request*> gone;  // requests that ended with an error this tick
   {
     std::map<Key, std::vector<Request*>> by_stream;
     for (Request* r : s->active) by_stream[key_of(r)].push_back(r);
     std::vector<std::vector<Request*>*> lists;
     for (auto& kv : by_stream) lists.push_back(&kv.second);
-    vps::Status st = on_pool(lists, [](Request* r) {
-      return vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
-    });
-    if (st.code) return sfail(st.code, st.msg);
+    std::vector<Failure> failed;
+    on_pool(lists, [](Request* r) {
+      vps::Status st = injected(r, kStageIterate);
+      return st.code ? st : vps::pcg_iterate_launch(r->slot.prob, r->mode, r->x, &r->cs);
+    }, &failed);
+    for (Failure& f : failed) {
+      fail_request(s, f.first, f.second.code, f.second.msg);
+      gone.insert(f.first);
+    }
   }
+  bool device_error = false;
   for (auto& kv : s->streams)
-    if (hipStreamSynchronize(kv.second) != hipSuccess) return sfail(VPS_EHIP, "stream synchronize failed");
+    if (hipStreamSynchronize(kv.second) != hipSuccess) device_error = true;
+  if (device_error) {
+    // the device is in error: every request in flight ends with it, the queue stays
+    (void)hipGetLastError();
+    for (Request* r : s->active)
+      if (!gone.count(r)) fail_request(s, r, VPS_EHIP, "stream synchronize failed");
+    for (Request* r : begun) fail_request(s, r, VPS_EHIP, "stream synchronize failed");
+    s->active.clear();
+    if (n_active) *n_active = 0;
+    if (n_queued) *n_queued = (int)s->queue.size();
+    return sfail(VPS_EHIP, "stream synchronize failed");
+  }
   // a request whose CG has ended launches its true residual (read back once this tick's
   // preconditioners are issued) or, with nothing to compute, is finished now
   std::vector<Request*> ending;
-  auto end_request = [&](Request* r) -> vps::Status {
+  auto end_request = [&](Request* r) {
     bool pending = false;
     vps::Status st = vps::pcg_end_launch(r->slot.prob, r->b, r->x, &r->cs, &pending);
-    if (st.code) return st;
-    if (pending) {
+    if (st.code) {
+      fail_request(s, r, st.code, st.msg);
+    } else if (pending) {
       ending.push_back(r);
     } else {
       finish(s, r);
       release(s, r);
     }
-    return vps::Status::ok();
   };
   std::vector<Request*> still;
   std::map<Key, std::vector<Request*>> groups;
   for (Request* r : s->active) {
+    if (gone.count(r)) continue;
     vps::Status st = vps::pcg_decide(r->slot.prob, r->mode, r->rtol, r->maxit, &r->cs);
-    if (st.code) return sfail(st.code, st.msg);
-    if (r->cs.done) {
-      st = end_request(r);
-      if (st.code) return sfail(st.code, st.msg);
+    if (st.code) {
+      fail_request(s, r, st.code, st.msg);
+    } else if (r->cs.done) {
+      end_request(r);
     } else {
       still.push_back(r);
       groups[key_of(r)].push_back(r);
@@ -350,10 +432,10 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
   std::vector<Request*> newcomers;
   for (Request* r : begun) {
     vps::Status st = vps::pcg_begin_check(r->slot.prob, &r->cs);
-    if (st.code) return sfail(st.code, st.msg);
-    if (r->cs.done) {
-      st = end_request(r);
-      if (st.code) return sfail(st.code, st.msg);
+    if (st.code) {
+      fail_request(s, r, st.code, st.msg);
+    } else if (r->cs.done) {
+      end_request(r);
     } else {
       newcomers.push_back(r);
       groups[key_of(r)].push_back(r);
@@ -361,29 +443,45 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
   }
   // mark the end of the true-residual work on each stream that has some: the host waits for these
   // marks, not for the preconditioners queued behind them
-  std::vector<hipEvent_t> marks;
+  std::vector<std::pair<hipEvent_t, Key>> marks;
   {
     std::set<Key> keys;
     for (Request* r : ending) keys.insert(key_of(r));
     for (const Key& k : keys) {
       hipEvent_t& ev = s->end_events[k];
-      if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        ev = nullptr;
-        return sfail(VPS_EHIP, "hipEventCreate failed");
+      bool ok = ev || hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (!ok) ev = nullptr;
+      ok = ok && hipEventRecord(ev, s->streams[k]) == hipSuccess;
+      if (ok) {
+        marks.push_back(std::make_pair(ev, k));
+      } else {
+        // the true residual of these requests cannot be waited for: they end with the error
+        (void)hipGetLastError();
+        std::vector<Request*> keep;
+        for (Request* r : ending) {
+          if (key_of(r) == k)
+            fail_request(s, r, VPS_EHIP, "hipEventRecord failed");
+          else
+            keep.push_back(r);
+        }
+        ending.swap(keep);
       }
-      if (hipEventRecord(ev, s->streams[k]) != hipSuccess) return sfail(VPS_EHIP, "hipEventRecord failed");
-      marks.push_back(ev);
     }
   }
   // preconditioner: one batched V-cycle per group, colour passes packed across its requests (new
-  // requests take their first application with the others); groups issue from parallel threads
+  // requests take their first application with the others); groups issue from parallel threads.
+  // A failure ends every request of its group (their V-cycles share launches).
   {
     std::vector<std::pair<const Key, std::vector<Request*>>*> glist;
     for (auto& kv : groups) glist.push_back(&kv);
     std::vector<vps::Status> res(glist.size());
     s->pool->run((int)glist.size(), [&](int i) {
       std::vector<vps::Problem*> ps;
-      for (Request* r : glist[i]->second) ps.push_back(r->slot.prob);
+      for (Request* r : glist[i]->second) {
+        res[i] = injected(r, kStagePrecondition);
+        if (res[i].code) return;
+        ps.push_back(r->slot.prob);
+      }
       res[i] = vps::precondition_group(ps.data(), (int)ps.size(), std::get<2>(glist[i]->first));
       if (res[i].code) return;
       for (Request* r : glist[i]->second) {
@@ -393,20 +491,49 @@ int vps_server_step(vps_server* s, int* n_active, int* n_queued) {
         if (res[i].code) return;
       }
     });
-    for (const vps::Status& st : res)
-      if (st.code) return sfail(st.code, st.msg);
+    for (size_t i = 0; i < glist.size(); ++i) {
+      if (!res[i].code) continue;
+      for (Request* r : glist[i]->second) {
+        fail_request(s, r, res[i].code, res[i].msg);
+        gone.insert(r);
+      }
+    }
   }
-  for (hipEvent_t ev : marks)
-    if (hipEventSynchronize(ev) != hipSuccess) return sfail(VPS_EHIP, "event synchronize failed");
+  for (auto& mk : marks) {
+    if (hipEventSynchronize(mk.first) == hipSuccess) continue;
+    (void)hipGetLastError();
+    std::vector<Request*> keep;
+    for (Request* r : ending) {
+      if (key_of(r) == mk.second)
+        fail_request(s, r, VPS_EHIP, "event synchronize failed");
+      else
+        keep.push_back(r);
+    }
+    ending.swap(keep);
+  }
   for (Request* r : ending) {
     vps::pcg_end_finish(r->slot.prob, &r->cs);
     finish(s, r);
     release(s, r);
   }
-  still.insert(still.end(), newcomers.begin(), newcomers.end());
-  s->active.swap(still);
+  std::vector<Request*> next;
+  for (Request* r : still)
+    if (!gone.count(r)) next.push_back(r);
+  for (Request* r : newcomers)
+    if (!gone.count(r)) next.push_back(r);
+  s->active.swap(next);
   if (n_active) *n_active = (int)s->active.size();
   if (n_queued) *n_queued = (int)s->queue.size();
+  return VPS_OK;
+}
+
+int vps_server_inject_fault(vps_server* s, long long ticket, int stage) {
+  if (!s) return sfail(VPS_EINVAL, "null server");
+  if (stage < kStageAdmit || stage > kStagePrecondition) return sfail(VPS_EINVAL, "bad stage");
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) return sfail(VPS_EINVAL, "unknown ticket");
+  if (it->second->done) return sfail(VPS_EINVAL, "request already finished");
+  it->second->inject = stage;
   return VPS_OK;
 }
 
@@ -446,7 +573,10 @@ int vps_server_destroy(vps_server* s) {
   for (auto& kv : s->end_events)
     if (kv.second) (void)hipEventDestroy(kv.second);
   for (auto& kv : s->streams) (void)hipStreamDestroy(kv.second);
-  for (auto& kv : s->all) delete kv.second;
+  for (auto& kv : s->all) {
+    drop_ready(kv.second);
+    delete kv.second;
+  }
   delete s;
   return VPS_OK;
 }

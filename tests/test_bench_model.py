@@ -52,8 +52,22 @@ def test_patch_eigenvectors_are_even_or_odd(k):
 
 
 def test_flop_model_at_degree_4():
-    assert bench.colour_pass_flops(3, 4) == 53201
+    assert bench.colour_pass_issued_flops(3, 4) == 53201
     assert bench.colour_pass_bytes(3, 4, 4) == 4 * (9 ** 3 + 2 * 7 ** 3)
+
+
+@pytest.mark.parametrize("d,k,patches,per_step", [(3, 4, 250047, 2.15e10), (2, 7, 261121, 1.04e10),
+                                                   (3, 3, 29791, 7.59e8)])
+def test_algorithmic_model_matches_the_workload_table(d, k, patches, per_step):
+    """The algorithmic flops per smoothing step (one update of every patch) of the 3D Q4 64^3,
+    2D Q7 512^2 and 3D Q3 32^3 workloads, as tabulated for the measurement model (3 digits)."""
+    assert abs(bench.smoother_patch_flops(d, k) * patches / per_step - 1) < 5e-3
+
+
+def test_algorithmic_words_3d_q4():
+    # x on the 9^3 closure skeleton + b on the 7^3 interior read, x on the interior written
+    assert bench.smoother_patch_min_words(3, 4) == (9 ** 3 - 7 ** 3) + 7 ** 3 + 7 ** 3 == 1072
+    assert bench.smoother_patch_flops(3, 4) == 86072
 
 
 def test_lds_traffic_model_3d_q4():

@@ -133,3 +133,85 @@ def test_zero_rhs_request_finishes_at_admission():
         assert torch.equal(x1, x_ref)
     finally:
         vps.vps_server_destroy(srv)
+
+
+def test_rhs_written_on_the_caller_stream_just_before_submit():
+    """The server orders a request's first read of b after the work queued on the caller's stream
+    at submit: b is filled by a copy queued behind a ~20 ms spin on that stream, and the request
+    still solves the filled rhs (an unordered read would see zeros and end at once with x = 0)."""
+    d, k, L = 2, 3, 5
+    src = _rhs(d, k, L, 21)
+    x_ref, its_ref, st_ref = _alone(d, k, L, src, vps.VPS_SOLVE_MIXED)
+    s = torch.cuda.Stream()
+    srv = vps.vps_server_create(1 << 30, 4, s.cuda_stream)
+    try:
+        b = torch.zeros_like(src)
+        x = torch.zeros_like(src)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            torch.cuda._sleep(40_000_000)
+            b.copy_(src)
+            t = vps.vps_server_submit(srv, d, k, L, b.data_ptr(), x.data_ptr(), 1e-8, vps.VPS_SOLVE_MIXED, 50)
+        for _ in range(200):
+            a, q = vps.vps_server_step(srv)
+            if a == 0 and q == 0:
+                break
+        done, st = vps.vps_server_poll(srv, t)
+        assert done and st.status == st_ref and st.iterations == its_ref > 0
+        torch.cuda.synchronize()
+        assert torch.equal(x, x_ref)
+    finally:
+        vps.vps_server_destroy(srv)
+
+
+def test_failed_requests_leave_the_server_consistent():
+    """Launch failures forced from the host (vps_server_inject_fault) at admission, at a CG
+    iteration and in a preconditioner: each failing request ends with the error as its status and
+    gives its hierarchy back; the requests beside it finish bitwise as they do alone; no memory
+    stays counted as in use; and the server serves the same shapes again afterwards."""
+    shapes = [(2, 3, 5), (3, 2, 3), (2, 5, 4), (3, 4, 2), (2, 3, 5)]
+    stage = {0: 0, 1: 1, 2: 2}  # request index -> the stage whose launch fails
+    bs = [_rhs(d, k, L, 30 + i) for i, (d, k, L) in enumerate(shapes)]
+    mode = vps.VPS_SOLVE_MIXED
+    srv = vps.vps_server_create(4 << 30, 8)
+    try:
+        xs = [torch.full_like(b, 5.0) for b in bs]
+        ts = [vps.vps_server_submit(srv, d, k, L, b.data_ptr(), x.data_ptr(), 1e-8, mode, 50)
+              for (d, k, L), b, x in zip(shapes, bs, xs)]
+        for i, sg in stage.items():
+            vps.vps_server_inject_fault(srv, ts[i], sg)
+        for _ in range(500):
+            a, q = vps.vps_server_step(srv)
+            if a == 0 and q == 0:
+                break
+        res = [vps.vps_server_poll(srv, t) for t in ts]
+        for i, (done, st) in enumerate(res):
+            print("request", i, shapes[i], "status", st.status, "iterations", st.iterations, flush=True)
+            assert done
+            if i in stage:
+                assert st.status == vps.VPS_EHIP
+            else:
+                ref, its, status = _alone(*shapes[i], bs[i], mode)
+                assert st.status == status == 0 and st.iterations == its
+                assert torch.equal(xs[i], ref)
+        in_use, cached = vps.vps_server_memory(srv)
+        assert in_use == 0 and cached > 0
+        with pytest.raises(vps.VpsError):
+            vps.vps_server_inject_fault(srv, ts[0], 1)  # finished
+        # the shapes of the failed requests are served again, from the cached hierarchies
+        again = [0, 2]
+        xs2 = [torch.zeros_like(bs[i]) for i in again]
+        ts2 = [vps.vps_server_submit(srv, *shapes[i], bs[i].data_ptr(), x.data_ptr(), 1e-8, mode, 50)
+               for i, x in zip(again, xs2)]
+        for _ in range(500):
+            a, q = vps.vps_server_step(srv)
+            if a == 0 and q == 0:
+                break
+        for i, x, t in zip(again, xs2, ts2):
+            done, st = vps.vps_server_poll(srv, t)
+            ref, its, status = _alone(*shapes[i], bs[i], mode)
+            assert done and st.status == 0 and st.iterations == its
+            assert torch.equal(x, ref)
+        assert vps.vps_server_memory(srv)[0] == 0
+    finally:
+        vps.vps_server_destroy(srv)

@@ -108,7 +108,13 @@ def test_config_solves_against_the_exact_solution(d, k, L, rtol, order):
     print("  iterations fp64 %d mixed %d; error vs exact: fp64 %.2e mixed %.2e; mixed vs fp64 %.2e"
           % (s64.iterations, s32.iterations, e64, e32, emx), flush=True)
     assert s64.status == 0 and s32.status == 0
-    assert s64.iterations == s32.iterations
+    # Both runs stop on the same test.  With the literal colour order the preconditioner is not
+    # symmetric, and at 2D Q7 512^2 its FP32 rounding leaves the mixed run's third residual just
+    # above 1e-10 where the FP64 run's is below it: the counts may differ by that one iteration.
+    if order == "reverse":
+        assert s64.iterations == s32.iterations
+    else:
+        assert abs(s64.iterations - s32.iterations) <= 1
     assert e64 <= 1e-8 and e32 <= 1e-8 and emx <= 1e-8
     P.close()
 
@@ -167,12 +173,21 @@ def test_table7_full_size(k, L, mode, request):
     assert st.status == 0
     r = P.residual(b, x)
     true = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
-    # residual entries on the sampled nodes: b_i - (A x)_i with the oracle's rows
-    rs = bs - mesh.operator_rows(d, k, L, coords, _DeviceGather(x))
-    e_rows = np.max(np.abs(_DeviceGather(r)[flat] - rs)) / bmax
-    print("  iterations %d, true residual %.3e (library %.3e), sampled residual rows vs oracle %.2e"
-          % (st.iterations, true, st.true_rel_residual, e_rows), flush=True)
-    assert e_rows <= 1e-12
+    # residual entries on the sampled nodes: b_i - (A x)_i with the oracle's rows.  At convergence
+    # the two terms cancel to about 1e-9 of |b_i|, so the difference of two correctly rounded
+    # evaluations is set by the magnitudes summed, S_i = |b_i| + sum |products of (A x)_i|: each
+    # side's error is at most gamma_n S_i with n = d (2k+1) + 2 the depth of the sum-factorised
+    # row (u = 2^-53), and the bar is twice that.
+    gx = _DeviceGather(x)
+    rs = bs - mesh.operator_rows(d, k, L, coords, gx)
+    mag = np.abs(bs) + mesh.operator_rows(d, k, L, coords, gx, absolute=True)
+    nd = d * (2 * k + 1) + 2
+    gamma = nd * 2.0 ** -53 / (1 - nd * 2.0 ** -53)
+    e_rows = np.max(np.abs(_DeviceGather(r)[flat] - rs) / np.maximum(mag, 1e-300))
+    print("  iterations %d, true residual %.3e (library %.3e), sampled residual rows vs oracle %.2e of "
+          "the summed magnitudes (bar %.2e)" % (st.iterations, true, st.true_rel_residual, e_rows, 2 * gamma),
+          flush=True)
+    assert e_rows <= 2 * gamma
     assert true <= 2e-9 and abs(true - st.true_rel_residual) <= 1e-3 * true
     if k == 3:
         pred = request.getfixturevalue("q3_error_extrapolation")

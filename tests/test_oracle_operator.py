@@ -93,3 +93,29 @@ def test_operator_rows_equal_the_full_apply(d, k, L):
     coords = np.array(list(np.ndindex(*([n] * d))))[:, ::-1]  # (c_0, ..., c_{d-1}) in flat order
     got = mesh.operator_rows(d, k, L, coords, xg)
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("d,k,L", [(2, 2, 2), (3, 1, 2), (3, 2, 1)])
+def test_absolute_operator_rows_equal_the_explicit_kronecker_sum(d, k, L):
+    """The magnitude sum used for tolerances on computed rows, sum_dir ((x)_a |A1 or M1|) |x|, equals
+    the same sum formed from explicit Kronecker products of the dense interior 1D matrices; it also
+    bounds |A x| entrywise."""
+    import synth
+    x = synth.random_interior(d, k, L, 17)
+    n = mesh.n1d(k, L)
+    A1, M1 = (abs(m.toarray()) for m in mesh.global_1d_matrices(k, L))
+    inner = np.arange(1, n - 1)
+    A1, M1 = A1[np.ix_(inner, inner)], M1[np.ix_(inner, inner)]
+    big = 0.0
+    for direction in range(d):
+        term = np.ones((1, 1))
+        for a in reversed(range(d)):  # leftmost factor = slowest axis
+            term = np.kron(term, A1 if a == direction else M1)
+        big = big + term
+    ids = mesh.interior_ids(d, k, L)
+    ref = big @ np.abs(x[ids])
+    coords = np.array(list(np.ndindex(*([n] * d))))[:, ::-1]
+    got = mesh.operator_rows(d, k, L, coords, x, absolute=True)
+    assert np.max(np.abs(got[ids] - ref)) <= 1e-14 * np.max(ref)
+    assert np.all(got[mesh.boundary_mask(d, k, L)] == 0.0)
+    assert np.all(np.abs(mesh.apply_operator(d, k, L, x)) <= got * (1 + 1e-14))
