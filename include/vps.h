@@ -150,6 +150,20 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
 /* r_coarse = P^T r_fine, P the embedding level-1 -> level (Sec. 2.1). fine_level >= 2. */
 int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, void* r_coarse);
 
+/* vps_restrict without a problem object and without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and result as vps_restrict for (dim, degree, fine_level).
+ * r_fine: device vector of n1d(fine_level)^dim values (boundary entries ignored); r_coarse:
+ * device vector of n1d(fine_level - 1)^dim values (boundary entries written 0); FP64 when prec =
+ * VPS_FP64, FP32 when VPS_FP32; both caller-owned.  hip_stream: the stream the launches go to
+ * (NULL: the null stream); nothing synchronises.  The intermediate lives in a static device
+ * array of 64 MiB per GPU held until the process ends, shared by every call on that GPU: calls
+ * that overlap on one GPU race.  VPS_EINVAL when the intermediate (n1d(fine)^(dim-1) *
+ * n1d(fine-1) values of the precision's size in 3D, n1d(fine) * n1d(fine-1) in 2D) exceeds it,
+ * on a bad shape or precision, or on a null vector; VPS_EHIP on a launch failure. */
+int vps_restrict_noalloc(int dim, int degree, int fine_level, int prec, const void* r_fine, void* r_coarse,
+                         void* hip_stream);
+
 /* x_fine += P e_coarse (Sec. 2.1, Alg. 1 coarse-grid correction). fine_level >= 2. */
 int vps_prolongate_add(vps_problem* p, int fine_level, int prec, const void* e_coarse, void* x_fine);
 

@@ -58,6 +58,7 @@ _SIGS = {
     "vps_smoother_apply": (_I, [_P, _I, _I, _I, _I, _P, _P]),
     "vps_color_pass": (_I, [_P, _I, _I, _I, _I, _P, _P]),
     "vps_restrict": (_I, [_P, _I, _I, _P, _P]),
+    "vps_restrict_noalloc": (_I, [_I, _I, _I, _I, _P, _P, _P]),
     "vps_prolongate_add": (_I, [_P, _I, _I, _P, _P]),
     "vps_coarse_solve": (_I, [_P, _I, _P, _P]),
     "vps_vcycle": (_I, [_P, _I, _P, _P]),
@@ -172,6 +173,10 @@ def vps_color_pass(h, level, prec, mode, color, b_ptr, x_ptr):
 
 def vps_restrict(h, fine_level, prec, rf_ptr, rc_ptr):
     return _call("vps_restrict", h, fine_level, prec, rf_ptr, rc_ptr)
+
+
+def vps_restrict_noalloc(dim, degree, fine_level, prec, rf_ptr, rc_ptr, hip_stream=None):
+    return _call("vps_restrict_noalloc", dim, degree, fine_level, prec, rf_ptr, rc_ptr, hip_stream)
 
 
 def vps_prolongate_add(h, fine_level, prec, e_ptr, x_ptr):

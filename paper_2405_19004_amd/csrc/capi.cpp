@@ -225,6 +225,28 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
   });
 }
 
+int vps_restrict_noalloc(int dim, int degree, int fine_level, int prec, const void* r_fine, void* r_coarse,
+                         void* hip_stream) {
+  return guarded([&]() -> int {
+    std::string why;
+    if (!valid_shape(dim, degree, fine_level, &why)) return fail(VPS_EINVAL, why);
+    if (fine_level < 2) return fail(VPS_EINVAL, "restriction needs fine_level >= 2");
+    if (int e = check_prec(prec)) return e;
+    const size_t need = (size_t)vps::restrict_scratch_elems(dim, degree, fine_level) * (prec == 0 ? 8 : 4);
+    if (need > vps::noalloc_scratch_bytes())
+      return fail(VPS_EINVAL, "restriction scratch of " + std::to_string(need) + " bytes exceeds the " +
+                                  std::to_string(vps::noalloc_scratch_bytes()) +
+                                  " bytes of the allocation-free entry point (use vps_restrict)");
+    if (!r_fine || !r_coarse) return fail(VPS_EINVAL, "null vector");
+    void* t = nullptr;
+    hipError_t e = vps::noalloc_scratch(&t);
+    if (e != hipSuccess) return fail(VPS_EHIP, std::string("scratch address: ") + hipGetErrorString(e));
+    e = vps::launch_restrict(vps::make_geom(dim, degree, fine_level), prec, r_fine, r_coarse, t,
+                             static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? VPS_OK : fail(VPS_EHIP, std::string("restrict launch: ") + hipGetErrorString(e));
+  });
+}
+
 int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, void* r_coarse) {
   return guarded([&]() -> int {
     if (int e = check_level(p, fine_level, 2)) return e;

@@ -24,6 +24,8 @@
 //
 // All kernels here write interior nodes only; boundary entries of outputs are
 // zeroed by zero_boundary_kernel where the caller needs it.
+#include <mutex>
+
 #include "device_common.hpp"
 #include "patch_tables_gen.hpp"
 #include "kernels.hpp"
@@ -1158,6 +1160,40 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
 hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st,
                            void* xc_zero) {
   VPS_DISPATCH(res_launch, fine, prec, rf, rc, st, t, xc_zero);
+}
+
+// ------------------------------------------- scratch of the allocation-free restriction
+//
+// One array per GPU, held from the module's load until the process ends.  Its name is a host-side
+// stand-in: host code passes only the device address looked up per device below.  Every call on a
+// GPU shares that GPU's array (calls that overlap on one GPU race); the restriction writes every
+// scratch entry it later uses, so nothing needs clearing between calls.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device ordinal
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // with this device current
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st) {

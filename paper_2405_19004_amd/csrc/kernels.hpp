@@ -74,6 +74,11 @@ inline long long restrict_scratch_elems(int dim, int k, int fine_level) {
   return dim == 2 ? nf * nc : nf * nc * nc;
 }
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st);
+// The allocation-free restriction's scratch: a static device array of noalloc_scratch_bytes()
+// bytes per GPU.  noalloc_scratch() returns its device address on the current device (looked up
+// once per device and kept).
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(void** out);
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);
 hipError_t launch_rhs_separable(const LevelGeom& g, int prec, int nterms, const double* G, const double* coef, void* b,
                                 hipStream_t st);

@@ -102,3 +102,16 @@ def test_server_rejects_oversize_request_on_host():
             v.vps_server_submit(s, 3, 4, 2, 1, 1, -1.0, v.VPS_SOLVE_MIXED, 50)
     finally:
         v.vps_server_destroy(s)
+
+
+def test_noalloc_restrict_refuses_on_the_host():
+    """Sizes beyond the static scratch, bad shapes and precisions are refused before any device
+    work (the pointers are never touched)."""
+    import paper_2405_19004_amd as v
+    L = v.lib()
+    assert L.vps_restrict_noalloc(3, 4, 7, v.VPS_FP64, 1, 1, None) == v.VPS_EINVAL
+    assert "exceeds" in v.last_error()
+    assert L.vps_restrict_noalloc(3, 4, 1, v.VPS_FP64, 1, 1, None) == v.VPS_EINVAL
+    assert L.vps_restrict_noalloc(4, 4, 3, v.VPS_FP64, 1, 1, None) == v.VPS_EINVAL
+    assert L.vps_restrict_noalloc(3, 4, 3, 2, 1, 1, None) == v.VPS_EINVAL
+    assert L.vps_restrict_noalloc(3, 4, 3, v.VPS_FP32, None, 1, None) == v.VPS_EINVAL
