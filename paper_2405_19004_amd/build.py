@@ -85,5 +85,70 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "sanitize")
+HOST_SOURCES = ["tables.cpp", "problem.cpp", "capi.cpp", "server.cpp"]
+
+
+def asan_runtime():
+    """Path of the compiler's shared AddressSanitizer runtime (host), or None."""
+    r = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode == 0 and os.path.isabs(path) and os.path.exists(path):
+        return path
+    base = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(_hipcc()))), "llvm", "lib", "clang")
+    for ver in sorted(os.listdir(base)) if os.path.isdir(base) else []:
+        cand = os.path.join(base, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return cand
+    return None
+
+
+def build_sanitized(verbose=False):
+    """libvps with its host code under AddressSanitizer and UndefinedBehaviorSanitizer.
+
+    The host sources are recompiled with the sanitizers (host compilation only: the device code of
+    every kernel is the regular build's), then linked with the regular objects of the kernel
+    sources.  For host-side tests without a GPU: load it through VPS_LIB with the ASan runtime
+    preloaded.  Returns the library path."""
+    for src in SOURCES:
+        if not os.path.exists(os.path.join(BUILD, os.path.splitext(src)[0] + ".o")):
+            build(verbose)
+            break
+    os.makedirs(SAN_DIR, exist_ok=True)
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer"]
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+
+    def one(src):
+        out = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [_hipcc()] + [f for f in COMMON if f != "-O3"] + flags + san + ["-c", os.path.join(CSRC, src), "-o", out]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("sanitized compile failed: %s\n%s" % (src, r.stderr[-8000:]))
+        return out
+
+    with cf.ThreadPoolExecutor(max_workers=len(HOST_SOURCES)) as ex:
+        objs = list(ex.map(one, HOST_SOURCES))
+    objs += [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES if s not in HOST_SOURCES]
+    lib = os.path.join(SAN_DIR, "libvps_sanitized.so")
+    # host link (clang++ of the same toolchain): the kernel objects carry their device code
+    clangxx = os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clangxx):
+        clangxx = shutil.which("clang++") or clangxx
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(_hipcc()))), "lib")
+    cmd = [clangxx, "-shared", "-fPIC", "-shared-libsan", "-fsanitize=address,undefined", "-o", lib] + objs + \
+        ["-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lamdhip64"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr[-8000:])
+    return lib
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
