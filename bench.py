@@ -289,8 +289,10 @@ def fmg_run(v, torch, P, kap, co):
 
 def variants_run(v, torch, P, b, stream):
     """Colour-pass forms on the finest level (Table 6 analogue): the fused kernel, the Boundary
-    kernel (Sec. 4.1.3) and the Separate pair (residual kernel, then the local-solve kernel), per
-    colour pass averaged over the 8 colours, and the V-cycle with each form."""
+    kernel (Sec. 4.1.3), the Separate pair (residual kernel, then the local-solve kernel) and the
+    fused kernel with its residual contractions on the matrix cores (FP32 only; in FP64 that mode
+    runs the fused kernel), per colour pass averaged over the 8 colours, and the V-cycle with each
+    form."""
     res = {}
     flags = v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY | v.VPS_FLAG_POST_SAME_ORDER
     for name, dt_ in (("fp32", torch.float32), ("fp64", torch.float64)):
@@ -299,13 +301,14 @@ def variants_run(v, torch, P, b, stream):
         r = torch.empty_like(bb)
         row = {}
         for form, mode in (("fused", v.VPS_MULTIPLICATIVE), ("boundary", v.VPS_MULTIPLICATIVE_BOUNDARY),
-                           ("separate", v.VPS_MULTIPLICATIVE_SEPARATE)):
+                           ("separate", v.VPS_MULTIPLICATIVE_SEPARATE), ("mfma", v.VPS_MULTIPLICATIVE_MFMA)):
             row[form + "_colour_pass_us"] = 1e6 * event_time(lambda: [P.color_pass(bb, xx, c, mode) for c in range(8)],
                                                              stream, 5) / 8
         row["separate_residual_kernel_us"] = 1e6 * event_time(lambda: P.residual(bb, xx, r), stream, 20)
         row["separate_solve_kernel_us"] = 1e6 * event_time(lambda: [P.color_pass(r, xx, c, v.VPS_ADDITIVE)
                                                                     for c in range(8)], stream, 5) / 8
-        for form, fl in (("boundary", v.VPS_FLAG_BOUNDARY_SMOOTHER), ("separate", v.VPS_FLAG_SEPARATE_SMOOTHER)):
+        for form, fl in (("boundary", v.VPS_FLAG_BOUNDARY_SMOOTHER), ("separate", v.VPS_FLAG_SEPARATE_SMOOTHER),
+                         ("mfma", v.VPS_FLAG_MFMA_SMOOTHER)):
             Q = v.Problem(P.dim, P.degree, P.L, flags | fl | v.VPS_FLAG_NO_SOLVER)
             row[form + "_vcycle_ms"] = 1e3 * event_time(lambda: Q.vcycle(bb, xx), stream, 5)
             Q.close()

@@ -60,7 +60,8 @@ enum vps_smooth {
   VPS_MULTIPLICATIVE = 0,
   VPS_ADDITIVE = 1,
   VPS_MULTIPLICATIVE_BOUNDARY = 2,
-  VPS_MULTIPLICATIVE_SEPARATE = 3
+  VPS_MULTIPLICATIVE_SEPARATE = 3,
+  VPS_MULTIPLICATIVE_MFMA = 4
 };
 enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
 
@@ -75,6 +76,7 @@ enum vps_solve { VPS_SOLVE_FP64 = 0, VPS_SOLVE_MIXED = 1 };
                                             (VPS_MULTIPLICATIVE_BOUNDARY below; Sec. 4.1.3) */
 #define VPS_FLAG_SEPARATE_SMOOTHER 0x40u /* V-cycles smooth in the "Separate" form
                                             (VPS_MULTIPLICATIVE_SEPARATE below; Sec. 4.1, Table 6) */
+#define VPS_FLAG_MFMA_SMOOTHER 0x80u /* V-cycles smooth with VPS_MULTIPLICATIVE_MFMA (below) */
 #define VPS_FLAG_GRAPHS 0x20u /* replay the CG preconditioner from a HIP graph captured on first use
                                  instead of launching its kernels one by one (same results; measured
                                  slower than direct launches for these solves, so off by default) */
@@ -140,7 +142,11 @@ int vps_residual(vps_problem* p, int level, int prec, const void* b, const void*
  * VPS_MULTIPLICATIVE_SEPARATE: the multiplicative smoother as two kernels per colour (the
  *   "Separate" kernels of Sec. 4.1, Table 6): the residual b - A x by the operator kernel into
  *   the level's residual buffer, then x^I += A_j^{-1} r^I.  Needs the hierarchy flag of `prec`.
- *   Equal to VPS_MULTIPLICATIVE up to rounding. */
+ *   Equal to VPS_MULTIPLICATIVE up to rounding.
+ * VPS_MULTIPLICATIVE_MFMA: VPS_MULTIPLICATIVE with the three contractions of the localised
+ *   residual (Sec. 3.1.1) on the matrix cores, for 3D degree 4 in FP32 on launches of at least
+ *   1024 workgroups; every other case runs VPS_MULTIPLICATIVE.  Equal to it up to rounding
+ *   (a measured variant: slower than the vector form here). */
 int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int reverse_colors, const void* b, void* x);
 
 /* One colour of Alg. 3 (mode as above) on `level`; color in 0..2^dim-1 where the colour of the

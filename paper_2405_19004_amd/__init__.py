@@ -17,9 +17,11 @@ LIB_PATH = os.environ.get("VPS_LIB") or os.path.join(_HERE, "libvps.so")
 VPS_OK, VPS_EINVAL, VPS_ENOMEM, VPS_EHIP, VPS_ENOCONV, VPS_EBREAKDOWN, VPS_ENOTFINITE, VPS_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 VPS_FP64, VPS_FP32 = 0, 1
 VPS_MULTIPLICATIVE, VPS_ADDITIVE, VPS_MULTIPLICATIVE_BOUNDARY, VPS_MULTIPLICATIVE_SEPARATE = 0, 1, 2, 3
+VPS_MULTIPLICATIVE_MFMA = 4
 VPS_SOLVE_FP64, VPS_SOLVE_MIXED = 0, 1
 VPS_FLAG_FP64_HIERARCHY, VPS_FLAG_FP32_HIERARCHY, VPS_FLAG_NO_SOLVER, VPS_FLAG_POST_SAME_ORDER = 0x1, 0x2, 0x4, 0x8
 VPS_FLAG_BOUNDARY_SMOOTHER, VPS_FLAG_GRAPHS, VPS_FLAG_SEPARATE_SMOOTHER = 0x10, 0x20, 0x40
+VPS_FLAG_MFMA_SMOOTHER = 0x80
 
 _STATUS_NAMES = {0: "VPS_OK", -1: "VPS_EINVAL", -2: "VPS_ENOMEM", -3: "VPS_EHIP", -4: "VPS_ENOCONV",
                  -5: "VPS_EBREAKDOWN", -6: "VPS_ENOTFINITE", -7: "VPS_EBUSY"}

@@ -205,7 +205,7 @@ int vps_smoother_apply(vps_problem* p, int level, int prec, int mode, int revers
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
     if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY &&
-        mode != VPS_MULTIPLICATIVE_SEPARATE)
+        mode != VPS_MULTIPLICATIVE_SEPARATE && mode != VPS_MULTIPLICATIVE_MFMA)
       return fail(VPS_EINVAL, "bad smoother mode");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");
     return from(vps::smoother(p->impl, level, prec, mode, reverse_colors != 0, b, x));
@@ -217,7 +217,7 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
     if (int e = check_level(p, level, 1)) return e;
     if (int e = check_prec(prec)) return e;
     if (mode != VPS_MULTIPLICATIVE && mode != VPS_ADDITIVE && mode != VPS_MULTIPLICATIVE_BOUNDARY &&
-        mode != VPS_MULTIPLICATIVE_SEPARATE)
+        mode != VPS_MULTIPLICATIVE_SEPARATE && mode != VPS_MULTIPLICATIVE_MFMA)
       return fail(VPS_EINVAL, "bad smoother mode");
     if (color < 0 || color >= (1 << p->impl->dim)) return fail(VPS_EINVAL, "color out of range");
     if (!b || !x) return fail(VPS_EINVAL, "null vector");

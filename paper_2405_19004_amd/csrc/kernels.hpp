@@ -27,7 +27,9 @@ hipError_t init_smoother_tables();
 
 // Colour-pass kernels: multiplicative (residual, then x^I += A_j^{-1} r), additive
 // (x^I += A_j^{-1} b^I) and Boundary (x^I = A_j^{-1} (b^I - A^{IB} x^B), x^I never read).
-enum { kModeMultiplicative = 0, kModeAdditive = 1, kModeBoundary = 2 };
+// kModeMfma: the multiplicative pass with the residual contractions on the matrix cores (3D Q4
+// FP32, default launch shape); elsewhere the same as kModeMultiplicative.
+enum { kModeMultiplicative = 0, kModeAdditive = 1, kModeBoundary = 2, kModeMfma = 4 };
 
 // One member of a packed colour-pass launch (see launch_colour_pass_group).
 struct ColourPassDesc {

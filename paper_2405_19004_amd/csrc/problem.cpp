@@ -27,7 +27,10 @@ namespace vps {
 // operator kernel, then the local solves of the additive kernel on that residual.
 constexpr int kSmoothSeparate = 3;
 inline int vcycle_mode(const Problem* p) {
-  return p->separate_smoother ? kSmoothSeparate : p->boundary_smoother ? kModeBoundary : kModeMultiplicative;
+  return p->separate_smoother   ? kSmoothSeparate
+         : p->boundary_smoother ? kModeBoundary
+         : p->mfma_smoother     ? kModeMfma
+                                : kModeMultiplicative;
 }
 
 long long level_nodes(int dim, int k, int level) {
@@ -129,6 +132,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   p->post_same_order = flags & 0x8u;
   p->boundary_smoother = flags & 0x10u;
   p->separate_smoother = flags & 0x40u;
+  p->mfma_smoother = flags & 0x80u;
   p->use_graphs = flags & 0x20u;
   p->lv.resize(L + 1);
   Plan pl = plan(dim, k, L, flags);

@@ -44,6 +44,7 @@ struct Problem {
   bool post_same_order = false;
   bool boundary_smoother = false;  // V-cycles smooth with the Boundary colour-pass kernel
   bool separate_smoother = false;  // V-cycles smooth in the Separate form (residual kernel + solve kernel)
+  bool mfma_smoother = false;      // V-cycles smooth with the matrix-core form where it exists
   // CG preconditioner per solve mode, captured once as a HIP graph and replayed every iteration
   // (the caller's stream may be the null stream, which cannot be captured: the graph is captured
   // on and replayed from a private stream ordered against the caller's by events)

@@ -957,14 +957,355 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   }
 }
 
+// ------------------------------------------------------------------ matrix-core form (3D, FP32)
+//
+// The three contractions of the localised residual r = b - Abar x (Sec. 3.1.1) are dense products
+// of a batch of patch lines with one small 1D matrix, so they run on the matrix cores
+// (v_mfma_f32_16x16x4f32: 16 lines x 4 inputs times 4 inputs x 16 outputs, FP32 products
+// accumulated in FP32); the fast-diagonalisation stages stay on the vector ALU, where the
+// eigenvectors' mirror symmetry halves their multiply-adds.  Lines of the workgroup's PPW
+// patches are stacked into 16-row tiles; the 1D matrices sit in per-lane registers (B operand):
+//   x0: lines (q, j2, j1) of the closure, inputs c (n, padded to a multiple of 4), outputs
+//       [M0 x | A0 x] (2m <= 16)                                  -> PM, PA [i0][line]
+//   x1: lines (q, i0, j2), inputs [PM(j1) | PA(j1)] (2n), outputs
+//       [M1 PM | A1 PM + M1 PA] (2m)                               -> U, V  [i1][line]
+//   x2: lines (q, i1, i0), inputs [U(j2) | V(j2)] (2n), outputs A2 U + M2 V (m); the vector ALU
+//       then forms r = b - h (A2 U + M2 V) and applies S^T along x2, as in colour_pass_lines.
+// Matrix-core operand layout (16x16x4, FP32): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 (l / 16) + i][l % 16] in accumulator register i.
+template <int K, int PPW>
+struct MfmaLds {
+  static constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m, nn = n * n;
+  static constexpr int KB0 = (n + 3) / 4, KB1 = (2 * n + 3) / 4;     // 4-wide input blocks
+  static constexpr int R0 = PPW * nn, R1 = PPW * m * n, R2 = PPW * mm;  // lines per stage
+  static constexpr int T0 = (R0 + 15) / 16, T1 = (R1 + 15) / 16, T2 = (R2 + 15) / 16;
+  static constexpr int RS = 2 * K * PPW + 1;
+  // closure rows padded so that a tile's 4-wide input blocks past column n stay inside the row (their
+  // B rows are zero; the values read there are zeros written by the closure load), and = 4 (mod 32)
+  // so that the 16 rows of a tile fall into distinct bank groups
+  static constexpr int RSX = pad32(RS + 4 * KB0 - n, 4);
+  static constexpr int LS0 = pad32(16 * T0, 20);   // PM / PA row: tile writes of 4 lines at once
+  static constexpr int LS1 = pad32(16 * T1, 4);    // U / V row
+  static constexpr int LS2 = pad32(16 * T2, 4);    // x2 result row
+  static constexpr int X = nn * RSX;
+  static constexpr int P = 2 * m * LS0;            // PM, PA
+  static constexpr int UV = 2 * m * LS1;           // U, V
+  static constexpr int Q = m * LS2;                // A2 U + M2 V
+  using Fd = SmootherLds<3, K, float, false, PPW>;  // strides of the diagonalisation stages
+  static constexpr int FD = m * (Fd::SI1 > Fd::SI0 ? (Fd::SI1 > Fd::SA1 ? (Fd::SI1 > Fd::SA2 ? Fd::SI1 : Fd::SA2)
+                                                                         : (Fd::SA1 > Fd::SA2 ? Fd::SA1 : Fd::SA2))
+                                                   : (Fd::SI0 > Fd::SA1 ? (Fd::SI0 > Fd::SA2 ? Fd::SI0 : Fd::SA2)
+                                                                         : (Fd::SA1 > Fd::SA2 ? Fd::SA1 : Fd::SA2)));
+  static constexpr int max2(int a, int b) { return a > b ? a : b; }
+  // region 0: X, then U/V, then the diagonalisation buffers of odd stages; region 1: PM/PA, then Q,
+  // then the even ones
+  static constexpr int A = max2(max2(X, UV), FD);
+  static constexpr int B = max2(max2(P, Q), FD);
+  static constexpr int total = A + B;
+};
+
+typedef float vps_f32x4 __attribute__((ext_vector_type(4)));
+
+template <int K, int PPW>
+__device__ __forceinline__ void colour_pass_mfma3(float* __restrict__ smem, const float* __restrict__ b,
+                                                  float* __restrict__ x, long long n1d, int p0, int p1, int p2,
+                                                  int cnt0, int cnt1, int groups0, float res_scale, float sol_scale,
+                                                  unsigned blk) {
+  using L = MfmaLds<K, PPW>;
+  using PT = gen::PatchTables<float, K>;
+  using Fd = typename L::Fd;
+  constexpr int n = L::n, m = L::m, mm = L::mm, nn = L::nn, RS = L::RS, RSX = L::RSX;
+  constexpr int NT = 256, NW = NT / 64;
+  static_assert(2 * m <= 16, "outputs of one contraction must fit the 16 matrix columns");
+  float* const rA = smem;         // X, then U/V, then odd diagonalisation buffers
+  float* const rB = smem + L::A;  // PM/PA, then Q, then even ones
+
+  const int g0 = blk % groups0;
+  const int rest = blk / groups0;
+  const int t1 = rest % cnt1, t2 = rest / cnt1;
+  const int tfirst = g0 * PPW;
+  const int P = min(PPW, cnt0 - tfirst);
+  const long long s0 = (long long)K * (p0 + 2 * tfirst);
+  const long long s1 = (long long)K * (p1 + 2 * t1);
+  const long long s2 = (long long)K * (p2 + 2 * t2);
+  const long long n1d2 = n1d * n1d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;  // matrix-core row (A) / column (B, D) and input sub-index
+  const int seg = 2 * K * P + 1;             // valid closure columns along x0
+  const int ld1 = (int)n1d, ld2 = (int)n1d2;
+  float* xo = x + (s2 * n1d2 + s1 * n1d + s0);
+  const float* bo = b + (s2 * n1d2 + s1 * n1d + s0);
+
+  // B operands (1D patch matrices; zero rows pad the inputs, zero columns the outputs)
+  float bx0[L::KB0], bx1[L::KB1], bx2[L::KB1];
+#pragma unroll
+  for (int kb = 0; kb < L::KB0; ++kb) {
+    const int k = 4 * kb + lk;
+    bx0[kb] = k >= n ? 0.f : lr < m ? PT::Mc[lr * n + k] : lr < 2 * m ? PT::Ac[(lr - m) * n + k] : 0.f;
+  }
+#pragma unroll
+  for (int kb = 0; kb < L::KB1; ++kb) {
+    const int k = 4 * kb + lk;
+    const bool pm = k < n, pa = k >= n && k < 2 * n;
+    const int c = pm ? k : k - n;
+    bx1[kb] = lr < m ? (pm ? PT::Mc[lr * n + c] : 0.f)
+                     : lr < 2 * m ? (pm ? PT::Ac[(lr - m) * n + c] : pa ? PT::Mc[(lr - m) * n + c] : 0.f) : 0.f;
+    bx2[kb] = lr < m ? (pm ? PT::Ac[lr * n + c] : pa ? PT::Mc[lr * n + c] : 0.f) : 0.f;
+  }
+
+  // Lines (q, i1, i0) of the vector stages: b on them is prefetched now (tasks past the last patch
+  // are clamped to it, so every load is in bounds)
+  constexpr int NB = PPW * mm;
+  constexpr int RB = (NB + NT - 1) / NT;
+  float bpre[RB][m], xpre[RB][m];
+  unsigned loff[RB];
+  int xoff[RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const int task = rr * NT + tid;
+    int q = task / mm;
+    const int r = task - q * mm, i1 = r / m, i0 = r - i1 * m;
+    q = min(q, P - 1);
+    loff[rr] = (unsigned)((1 + i1) * ld1 + 2 * K * q + 1 + i0) * (unsigned)sizeof(float);
+    xoff[rr] = (n + 1 + i1) * RSX + 2 * K * q + 1 + i0;  // node (i = 0) in the LDS closure
+#pragma unroll
+    for (int i = 0; i < m; ++i) bpre[rr][i] = ld_lane(bo + ld2 + i * ld2, loff[rr]);
+  }
+
+  // ---- closure -> X [j2][j1][c]; Dirichlet nodes, and columns past the workgroup's last patch, are 0
+  {
+    float* X = rA;
+    const bool lo1 = s1 == 0, hi1 = s1 + n - 1 == n1d - 1;
+    const bool lo2 = s2 == 0, hi2 = s2 + n - 1 == n1d - 1;
+    for (int w = tid; w < RSX * n; w += NT) {
+      const int j1 = w / RSX, c = w - j1 * RSX;
+      const int cl = min(c, seg - 1);
+      const long long gc = s0 + cl;
+      const bool bad = c >= seg || gc == 0 || gc == n1d - 1 || (j1 == 0 && lo1) || (j1 == n - 1 && hi1);
+      const unsigned base = (unsigned)(j1 * ld1 + cl) * (unsigned)sizeof(float);
+      float v[n];
+#pragma unroll
+      for (int j = 0; j < n; ++j) v[j] = ld_lane(xo + j * ld2, base);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        const bool zero = bad || (j == 0 && lo2) || (j == n - 1 && hi2);
+        X[(j * n + j1) * RSX + c] = zero ? 0.f : v[j];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+#pragma unroll
+    for (int i = 0; i < m; ++i) xpre[rr][i] = rA[xoff[rr] + i * n * RSX];  // old x^I (never Dirichlet)
+  }
+
+  // ---- x0 on the matrix cores: lines (q, j2, j1) -> PM, PA [i0][line]
+  {
+    const float* X = rA;
+    float* PM = rB;
+    for (int t = wave; t < L::T0; t += NW) {
+      const int row = min(16 * t + lr, L::R0 - 1);
+      const int q = row / nn, rem = row - q * nn;
+      const int a = lds_base(rem * RSX + 2 * K * q + lk);
+      vps_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < L::KB0; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(X[a + 4 * kb], bx0[kb], acc, 0, 0, 0);
+      if (lr < 2 * m) *reinterpret_cast<vps_f32x4*>(PM + lr * L::LS0 + 16 * t + 4 * lk) = acc;
+    }
+  }
+  __syncthreads();
+  // ---- x1 on the matrix cores: lines (q, i0, j2), inputs PM(j1), PA(j1) -> U, V [i1][line]
+  {
+    const float* PM = rB;
+    float* U = rA;
+    int koff[L::KB1];
+#pragma unroll
+    for (int kb = 0; kb < L::KB1; ++kb) {
+      const int k = 4 * kb + lk;
+      koff[kb] = k < n ? k : k < 2 * n ? m * L::LS0 + (k - n) : 0;
+    }
+    for (int t = wave; t < L::T1; t += NW) {
+      const int row = min(16 * t + lr, L::R1 - 1);
+      const int q = row / (m * n), rem = row - q * (m * n);
+      const int i0 = rem / n, j2 = rem - i0 * n;
+      const int a = lds_base(i0 * L::LS0 + q * nn + j2 * n);
+      vps_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < L::KB1; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(PM[a + koff[kb]], bx1[kb], acc, 0, 0, 0);
+      if (lr < 2 * m) *reinterpret_cast<vps_f32x4*>(U + lr * L::LS1 + 16 * t + 4 * lk) = acc;
+    }
+  }
+  __syncthreads();
+  // ---- x2 on the matrix cores: lines (q, i1, i0), inputs U(j2), V(j2) -> Q = A2 U + M2 V [i2][line]
+  {
+    const float* U = rA;
+    float* Q = rB;
+    int koff[L::KB1];
+#pragma unroll
+    for (int kb = 0; kb < L::KB1; ++kb) {
+      const int k = 4 * kb + lk;
+      koff[kb] = k < n ? k : k < 2 * n ? m * L::LS1 + (k - n) : 0;
+    }
+    for (int t = wave; t < L::T2; t += NW) {
+      const int row = min(16 * t + lr, L::R2 - 1);
+      const int q = row / mm, rem = row - q * mm;
+      const int i1 = rem / m, i0 = rem - i1 * m;
+      const int a = lds_base(i1 * L::LS1 + (q * m + i0) * n);
+      vps_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < L::KB1; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(U[a + koff[kb]], bx2[kb], acc, 0, 0, 0);
+      if (lr < m) *reinterpret_cast<vps_f32x4*>(Q + lr * L::LS2 + 16 * t + 4 * lk) = acc;
+    }
+  }
+  __syncthreads();
+
+  constexpr int SI1 = Fd::SI1, SI0 = Fd::SI0, SA1 = Fd::SA1, SA2 = Fd::SA2;
+  // ---- r = b - h (A2 U + M2 V), then S^T along x2: lines (q, i1, i0)
+  {
+    const float* Q = rB;
+    float* W4 = rA;  // [i1][q][a2][i0]
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / mm, r = task - q * mm;
+      const int i1 = r / m, i0 = r - i1 * m;
+      if (task < NB && q < P) {
+        float res[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) res[i] = fma(-res_scale, Q[i * L::LS2 + task], bpre[rr][i]);
+        float t[m];
+        apply_st<float, K>(res, t);
+        const int o = lds_base(i1 * SI1 + q * mm + i0);
+#pragma unroll
+        for (int a = 0; a < m; ++a) W4[o + a * m] = t[a];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- S^T along x1: lines (q, a2, i0)
+  {
+    const float* W4 = rA;
+    float* W5 = rB;  // [i0][q][a2][a1]
+    for (int base = 0; base < PPW * mm; base += NT) {
+      const int task = base + tid;
+      const int q = task / mm, r = task - q * mm;
+      const int a2 = r / m, i0 = r - a2 * m;
+      if (task < PPW * mm && q < P) {
+        float in[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) in[i] = W4[i * SI1 + task];
+        const int o = lds_base(i0 * SI0 + q * mm + a2 * m);
+        float t[m];
+        apply_st<float, K>(in, t);
+#pragma unroll
+        for (int a = 0; a < m; ++a) W5[o + a] = t[a];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- S^T along x0, 1/(lam2 + lam1 + lam0), S along x0: lines (q, a2, a1)
+  {
+    const float* W5 = rB;
+    float* W6 = rA;  // [a1][q][a2][i0]
+    for (int base = 0; base < PPW * mm; base += NT) {
+      const int task = base + tid;
+      const int q = task / mm, r = task - q * mm;
+      const int a2 = r / m, a1 = r - a2 * m;
+      if (task < PPW * mm && q < P) {
+        const DevTables<float>& tb = tab_fresh<float>(K);
+        float in[m], z[m];
+#pragma unroll
+        for (int i = 0; i < m; ++i) in[i] = W5[i * SI0 + task];
+        const int li = (a2 * m + a1) * m;
+        apply_st<float, K>(in, z);
+#pragma unroll
+        for (int a = 0; a < m; ++a) z[a] *= tb.inv3[li + a];
+        const int o = lds_base(a1 * SA1 + q * mm + a2 * m);
+        float w[m];
+        apply_s<float, K>(z, w);
+#pragma unroll
+        for (int i = 0; i < m; ++i) W6[o + i] = w[i];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- S along x1: lines (q, a2, i0)
+  {
+    const float* W6 = rA;
+    float* W7 = rB;  // [a2][q][i1][i0]
+    for (int base = 0; base < PPW * mm; base += NT) {
+      const int task = base + tid;
+      const int q = task / mm, r = task - q * mm;
+      const int a2 = r / m, i0 = r - a2 * m;
+      if (task < PPW * mm && q < P) {
+        float in[m];
+#pragma unroll
+        for (int a = 0; a < m; ++a) in[a] = W6[a * SA1 + task];
+        const int o = lds_base(a2 * SA2 + q * mm + i0);
+        float w[m];
+        apply_s<float, K>(in, w);
+#pragma unroll
+        for (int i = 0; i < m; ++i) W7[o + i * m] = w[i];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- S along x2 and x^I += correction / h, straight to global: lines (q, i1, i0)
+  {
+    const float* W7 = rB;
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / mm;
+      if (task < NB && q < P) {
+        float in[m];
+#pragma unroll
+        for (int a = 0; a < m; ++a) in[a] = W7[a * SA2 + task];
+        float w[m];
+        apply_s<float, K>(in, w);
+#pragma unroll
+        for (int i = 0; i < m; ++i) st_lane(xo + (1 + i) * ld2, loff[rr], fma(sol_scale, w[i], xpre[rr][i]));
+      }
+    }
+  }
+}
+
 // LDS words of one workgroup of a colour pass.  The x2-first form (colour_pass_mult3) serves the 3D
 // multiplicative pass in FP64, where it measured 3-9% faster than the closure-through-LDS form; in
 // FP32 the two measured within 2% and the closure form is kept (its b loads stay within one node
 // plane per access).
+// Patches per workgroup of the matrix-core form (3D Q4, FP32, multiplicative), 256 threads.
+constexpr int kMfmaPPW = 4;
+template <int D, int K, typename T>
+struct HasMfmaForm {
+  static constexpr bool value = D == 3 && K == 4 && sizeof(T) == 4;
+};
+template <int D, int K, typename T, int MODE>
+struct UsesMfma {
+  static constexpr bool value = HasMfmaForm<D, K, T>::value && MODE == kModeMfma;
+};
+// Default launch shape per form: patches per workgroup and threads.
+template <int D, int K, typename T, int MODE>
+struct ColourShape {
+  static constexpr bool kMfma = UsesMfma<D, K, T, MODE>::value;
+  static constexpr int PPW = kMfma ? kMfmaPPW : SmootherShape<D, K>::PPW;
+  static constexpr int NT = kMfma ? 256 : SmootherShape<D, K>::NT;
+};
+// Threads of a launch with PPW patches per workgroup (small launches take the vector form with the
+// latency shape).
+template <int D, int K, typename T, int MODE, int PPW>
+struct ColourNT {
+  static constexpr int value = UsesMfma<D, K, T, MODE>::value && PPW == kMfmaPPW ? 256 : SmootherShape<D, K>::NT;
+};
+
 template <int D, int K, typename T, int MODE, int PPW>
 struct ColourLds {
+  static constexpr bool kMfma = UsesMfma<D, K, T, MODE>::value && PPW == kMfmaPPW;
   static constexpr bool kMult3 = D == 3 && MODE == kModeMultiplicative && sizeof(T) == 8;
-  static constexpr int value = kMult3 ? Mult3Lds<K, PPW>::total : SmootherLds<D, K, T, MODE == kModeAdditive, PPW>::total;
+  static constexpr int value = kMfma ? MfmaLds<K, PPW>::total
+                               : kMult3 ? Mult3Lds<K, PPW>::total
+                                        : SmootherLds<D, K, T, MODE == kModeAdditive, PPW>::total;
 };
 
 // One workgroup's share of a colour pass: the 3D multiplicative pass in FP64 contracts the closure
@@ -973,7 +1314,9 @@ template <int D, int K, typename T, int MODE, int PPW>
 __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T* __restrict__ b, T* __restrict__ x,
                                                   long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
                                                   int groups0, T res_scale, T sol_scale, unsigned blk) {
-  if constexpr (ColourLds<D, K, T, MODE, PPW>::kMult3)
+  if constexpr (ColourLds<D, K, T, MODE, PPW>::kMfma)
+    colour_pass_mfma3<K, PPW>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale, blk);
+  else if constexpr (ColourLds<D, K, T, MODE, PPW>::kMult3)
     colour_pass_mult3<K, T, PPW>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale, blk);
   else
     colour_pass_lines<D, K, T, MODE, PPW>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
@@ -981,7 +1324,7 @@ __device__ __forceinline__ void colour_pass_block(T* __restrict__ smem, const T*
 }
 
 template <int D, int K, typename T, int MODE, int PPW>
-__global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
+__global__ __launch_bounds__((ColourNT<D, K, T, MODE, PPW>::value)) void colour_pass_kernel(
     const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
     int groups0, T res_scale, T sol_scale) {
   __shared__ T smem[ColourLds<D, K, T, MODE, PPW>::value];
@@ -991,9 +1334,8 @@ __global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_kernel(
 
 // Several colour passes of the same (dim, degree, precision, colour) on different vectors and
 // levels in one launch: entry e owns blocks [begin[e], begin[e+1]).
-template <int D, int K, typename T, int MODE>
-__global__ __launch_bounds__((SmootherShape<D, K>::NT)) void colour_pass_group_kernel(ColourPassGroup grp) {
-  constexpr int PPW = SmootherShape<D, K>::PPW;
+template <int D, int K, typename T, int MODE, int PPW>
+__global__ __launch_bounds__((ColourNT<D, K, T, MODE, PPW>::value)) void colour_pass_group_kernel(ColourPassGroup grp) {
   __shared__ T smem[ColourLds<D, K, T, MODE, PPW>::value];
   const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
   int e = 0;
@@ -1031,7 +1373,7 @@ struct ColourGrid {
 template <int D, int K, typename T, int MODE, int PPW>
 static hipError_t launch_shape(const LevelGeom& g, const ColourGrid<D, K>& cg, const void* b, void* x,
                                hipStream_t st) {
-  constexpr int NT = SmootherShape<D, K>::NT;
+  constexpr int NT = ColourNT<D, K, T, MODE, PPW>::value;
   // Abar_h = h^(d-2) Abar_1 ; A_j,h^{-1} = h^(2-d) A_j,1^{-1}
   const T res_scale = (T)(D == 3 ? g.h : 1.0);
   const T sol_scale = (T)(D == 3 ? 1.0 / g.h : 1.0);
@@ -1043,8 +1385,8 @@ static hipError_t launch_shape(const LevelGeom& g, const ColourGrid<D, K>& cg, c
 
 template <int D, int K, typename T, int MODE>
 static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
-  constexpr int PPW = SmootherShape<D, K>::PPW, LPPW = LatencyPPW<D, K>::value;
-  const ColourGrid<D, K> cg(g, colour);
+  constexpr int PPW = ColourShape<D, K, T, MODE>::PPW, LPPW = LatencyPPW<D, K>::value;
+  const ColourGrid<D, K> cg(g, colour, PPW);
   if (!cg.ok) return hipErrorInvalidConfiguration;
   if (cg.blocks == 0) return hipSuccess;
   if constexpr (LPPW < PPW) {
@@ -1057,21 +1399,36 @@ static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void
   return launch_shape<D, K, T, MODE, PPW>(g, cg, b, x, st);
 }
 
+// True when a stand-alone pass of this colour and level runs the matrix-core form (launch_one: the
+// default shape, not the small-launch one).  A packed launch must give each member the arithmetic of
+// its stand-alone pass, so that a result does not depend on the requests it is served with.
 template <int D, int K, typename T, int MODE>
-static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, hipStream_t st) {
-  constexpr int NT = SmootherShape<D, K>::NT;
+static bool member_uses_mfma(const LevelGeom& g, int colour) {
+  if constexpr (!UsesMfma<D, K, T, MODE>::value) {
+    return false;
+  } else {
+    const ColourGrid<D, K> cg(g, colour, kMfmaPPW);
+    return cg.blocks >= kLatencyBlocks;
+  }
+}
+
+// The members with mfma == member_uses_mfma, in launches of PPW patches per workgroup.
+template <int D, int K, typename T, int MODE, int PPW>
+static hipError_t launch_group_form(int colour, const ColourPassMember* mem, int nm, bool mfma, hipStream_t st) {
+  constexpr int NT = ColourNT<D, K, T, MODE, PPW>::value;
   ColourPassGroup grp;
   grp.n = 0;
   long long total = 0;
   auto flush = [&]() -> hipError_t {
     if (grp.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((colour_pass_group_kernel<D, K, T, MODE>), dim3((unsigned)total), dim3(NT), 0, st, grp);
+    hipLaunchKernelGGL((colour_pass_group_kernel<D, K, T, MODE, PPW>), dim3((unsigned)total), dim3(NT), 0, st, grp);
     grp.n = 0;
     total = 0;
     return hipGetLastError();
   };
   for (int i = 0; i < nm; ++i) {
-    const ColourGrid<D, K> cg(mem[i].g, colour);
+    if (member_uses_mfma<D, K, T, MODE>(mem[i].g, colour) != mfma) continue;
+    const ColourGrid<D, K> cg(mem[i].g, colour, PPW);
     if (!cg.ok) return hipErrorInvalidConfiguration;
     if (cg.blocks == 0) continue;
     if (grp.n == kMaxGroup || total + cg.blocks > 0x7fffffffLL) {
@@ -1096,12 +1453,25 @@ static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, 
   return flush();
 }
 
+template <int D, int K, typename T, int MODE>
+static hipError_t launch_group(int colour, const ColourPassMember* mem, int nm, hipStream_t st) {
+  constexpr int PPW = SmootherShape<D, K>::PPW;
+  if constexpr (UsesMfma<D, K, T, MODE>::value) {
+    hipError_t e = launch_group_form<D, K, T, MODE, kMfmaPPW>(colour, mem, nm, true, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_group_form<D, K, T, MODE, PPW>(colour, mem, nm, false, st);
+}
+
 template <int D, int K, typename T>
 static hipError_t dispatch_mode(const LevelGeom& g, int mode, int colour, const void* b, void* x, hipStream_t st) {
   switch (mode) {
     case kModeMultiplicative: return launch_one<D, K, T, kModeMultiplicative>(g, colour, b, x, st);
     case kModeAdditive: return launch_one<D, K, T, kModeAdditive>(g, colour, b, x, st);
     case kModeBoundary: return launch_one<D, K, T, kModeBoundary>(g, colour, b, x, st);
+    case kModeMfma:
+      if constexpr (HasMfmaForm<D, K, T>::value) return launch_one<D, K, T, kModeMfma>(g, colour, b, x, st);
+      return launch_one<D, K, T, kModeMultiplicative>(g, colour, b, x, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1144,6 +1514,12 @@ static hipError_t group_prec(int prec, int mode, int colour, const ColourPassMem
   if (mode == kModeBoundary)
     return prec == 0 ? launch_group<D, K, double, kModeBoundary>(colour, m, nm, st)
                      : launch_group<D, K, float, kModeBoundary>(colour, m, nm, st);
+  if (mode == kModeMfma) {
+    if constexpr (HasMfmaForm<D, K, float>::value)
+      if (prec == 1) return launch_group<D, K, float, kModeMfma>(colour, m, nm, st);
+    return prec == 0 ? launch_group<D, K, double, kModeMultiplicative>(colour, m, nm, st)
+                     : launch_group<D, K, float, kModeMultiplicative>(colour, m, nm, st);
+  }
   return hipErrorInvalidValue;
 }
 

@@ -192,3 +192,51 @@ def test_transfer_several_tiles(d, k, L, prec):
     e_pro = maxrel(host(xt), ref)
     assert e_pro <= tol
     print("  max error / max |ref|: restrict %.2e prolongate %.2e" % (e_res, e_pro), flush=True)
+
+
+# ------------------------------------------------------------------ matrix-core form of the colour pass
+
+@pytest.mark.parametrize("d,k,L", [(3, 4, 6), (3, 4, 5)])
+def test_mfma_colour_pass_every_patch(d, k, L):
+    """VPS_MULTIPLICATIVE_MFMA (residual contractions on the matrix cores, 3D Q4 FP32, launches of
+    at least 1024 workgroups; smaller colours take the vector form) against the oracle, every patch
+    of every colour, same bar as the vector form."""
+    dtype, tol = F32, TOL32[d]
+    P = problem(d, k, L)
+    b = as_seen(synth.random_interior(d, k, L, 131), dtype)
+    x = as_seen(synth.random_interior(d, k, L, 132), dtype)
+    bd = to_dev(poisoned(b, d, k, L), dtype)
+    x_pois = poisoned(x, d, k, L)
+    worst = 0.0
+    for c in range(2 ** d):
+        case("mfma colour pass", d, k, L, "colour", c)
+        verts = mesh.patches_of_colour(d, L, c)
+        C = mesh.patch_box_ids_many(d, k, L, verts, interior=False)
+        I = mesh.patch_box_ids_many(d, k, L, verts, interior=True)
+        ref = smoother.patch_update_local_many(d, k, L, x[C], b[I])
+        outside = np.ones(x.shape, dtype=bool)
+        outside[I.reshape(-1)] = False
+        xt = to_dev(x_pois, dtype)
+        P.color_pass(bd, xt, c, vps.VPS_MULTIPLICATIVE_MFMA)
+        got = host(xt)
+        e = maxrel(got[I], ref)
+        worst = max(worst, e)
+        assert e <= tol, (c, e)
+        assert np.array_equal(got[outside], x_pois[outside], equal_nan=True), c
+    print("  max error / max |ref|: %.2e" % worst, flush=True)
+
+
+@pytest.mark.parametrize("d,k,L,dtype", [(3, 3, 5, F32), (3, 4, 6, F64), (2, 4, 6, F32)])
+def test_mfma_mode_elsewhere_is_the_vector_pass(d, k, L, dtype):
+    """Where the matrix-core form does not exist, VPS_MULTIPLICATIVE_MFMA runs the vector pass: bit
+    for bit the same as VPS_MULTIPLICATIVE."""
+    case("mfma fallback", d, k, L, dtype)
+    P = problem(d, k, L)
+    b = to_dev(synth.random_interior(d, k, L, 141), dtype)
+    x0 = to_dev(synth.random_interior(d, k, L, 142), dtype)
+    for c in range(2 ** d):
+        x1, x2 = x0.clone(), x0.clone()
+        P.color_pass(b, x1, c, vps.VPS_MULTIPLICATIVE)
+        P.color_pass(b, x2, c, vps.VPS_MULTIPLICATIVE_MFMA)
+        torch.cuda.synchronize()
+        assert torch.equal(x1, x2), c

@@ -196,3 +196,26 @@ def test_table7_full_size(k, L, mode, request):
         assert abs(err / pred - 1) < 0.1
     del b, x, r
     P.close()
+
+
+def test_mfma_smoother_solve_at_3d_q4_64():
+    """The mixed solve of 3D Q4 64^3 with VPS_FLAG_MFMA_SMOOTHER (the V-cycle's FP32 colour passes on
+    the matrix cores) against the exact discrete solution, with the benchmark spec's bound for mixed
+    precision, and against the vector-form solve."""
+    d, k, L = 3, 4, 6
+    case("mfma smoother solve", d, k, L)
+    kap, co = synth.fourier_modes(d, seed=1)
+    b = rhs.rhs_sine_modes(d, k, L, kap, co)
+    exact = direct.exact_solve(d, k, L, b)
+    P = vps.Problem(d, k, L, BOTH | vps.VPS_FLAG_POST_SAME_ORDER | vps.VPS_FLAG_MFMA_SMOOTHER)
+    Q = vps.Problem(d, k, L, BOTH | vps.VPS_FLAG_POST_SAME_ORDER)
+    bt = P.rhs_sine_modes(kap, co)
+    xm, sm = P.pcg_solve(bt, rtol=1e-8, mode=vps.VPS_SOLVE_MIXED)
+    xv, sv = Q.pcg_solve(bt, rtol=1e-8, mode=vps.VPS_SOLVE_MIXED)
+    em, ev = rel(host(xm), exact), rel(host(xv), exact)
+    print("  iterations mfma %d vector %d; error vs exact mfma %.2e vector %.2e" % (sm.iterations, sv.iterations, em, ev),
+          flush=True)
+    assert sm.status == 0 and abs(sm.iterations - sv.iterations) <= 1
+    assert em <= 1e-8
+    P.close()
+    Q.close()
