@@ -224,6 +224,17 @@ int vps_synchronize(vps_problem* p);
 /* Message of the last failing call on this thread ("" if none). */
 const char* vps_last_error(void);
 
+/* Host-side check of the launch geometry of a hierarchy with fine level fine_level (no device
+ * work; for tests and for callers sizing very large problems): on every level, every workgroup of
+ * every colour pass (all colours, every launch shape the library uses) maps to patches of that
+ * colour inside the grid, the workgroups cover each patch exactly once, and each workgroup's
+ * farthest closure node is within the kernels' 32-bit byte offsets; every operator, restriction
+ * and prolongation launch fits its launcher's limits (grid sizes, 32-bit offsets).  The patch
+ * grid is the colouring of Sec. 2.2 (Fig. 2); the operator and transfers those of Secs. 2.1, 2.3.
+ * *blocks_checked (may be NULL) receives the number of colour-pass workgroups enumerated.
+ * VPS_OK, or VPS_EINVAL with the first violation in vps_last_error(). */
+int vps_launch_geometry_check(int dim, int degree, int fine_level, long long* blocks_checked);
+
 /* Host-side 1D tables for degree k (reference cell [0,1]) written to `out`, for tests:
  * which = 0: Gauss-Lobatto nodes (k+1); 1: reference stiffness (k+1)^2; 2: reference mass;
  * 3: patch eigenvectors S ((2k-1)^2, row-major, S^T M S = I, two-cell patch of unit cells);

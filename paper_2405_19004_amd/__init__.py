@@ -61,6 +61,7 @@ _SIGS = {
     "vps_color_pass": (_I, [_P, _I, _I, _I, _I, _P, _P]),
     "vps_restrict": (_I, [_P, _I, _I, _P, _P]),
     "vps_restrict_noalloc": (_I, [_I, _I, _I, _I, _P, _P, _P]),
+    "vps_launch_geometry_check": (_I, [_I, _I, _I, ctypes.POINTER(_LL)]),
     "vps_prolongate_add": (_I, [_P, _I, _I, _P, _P]),
     "vps_coarse_solve": (_I, [_P, _I, _P, _P]),
     "vps_vcycle": (_I, [_P, _I, _P, _P]),
@@ -175,6 +176,13 @@ def vps_color_pass(h, level, prec, mode, color, b_ptr, x_ptr):
 
 def vps_restrict(h, fine_level, prec, rf_ptr, rc_ptr):
     return _call("vps_restrict", h, fine_level, prec, rf_ptr, rc_ptr)
+
+
+def vps_launch_geometry_check(dim, degree, fine_level):
+    """Host-side check of every launch of a hierarchy; returns the colour-pass workgroups checked."""
+    n = _LL()
+    _call("vps_launch_geometry_check", dim, degree, fine_level, ctypes.byref(n))
+    return n.value
 
 
 def vps_restrict_noalloc(dim, degree, fine_level, prec, rf_ptr, rc_ptr, hip_stream=None):

@@ -225,6 +225,21 @@ int vps_color_pass(vps_problem* p, int level, int prec, int mode, int color, con
   });
 }
 
+int vps_launch_geometry_check(int dim, int degree, int fine_level, long long* blocks_checked) {
+  return guarded([&]() -> int {
+    std::string why;
+    if (!valid_shape(dim, degree, fine_level, &why)) return fail(VPS_EINVAL, why);
+    long long blocks = 0;
+    for (int lvl = 1; lvl <= fine_level; ++lvl) {
+      const vps::LevelGeom g = vps::make_geom(dim, degree, lvl);
+      if (!vps::check_colour_launches(g, &blocks, &why) || !vps::check_grid_launches(g, &why))
+        return fail(VPS_EINVAL, "level " + std::to_string(lvl) + ": " + why);
+    }
+    if (blocks_checked) *blocks_checked = blocks;
+    return VPS_OK;
+  });
+}
+
 int vps_restrict_noalloc(int dim, int degree, int fine_level, int prec, const void* r_fine, void* r_coarse,
                          void* hip_stream) {
   return guarded([&]() -> int {

@@ -67,6 +67,31 @@ struct LevelGeom {
   double h;
 };
 
+// Workgroup `blk` of a colour pass: PPW patches consecutive along x0 inside the colour whose patch
+// grid is described by the vertex parities p[], the patch counts cnt0, cnt1 (and the third axis in
+// 3D) and the workgroups per x0 row groups0.  The kernels and the host-side launch check both take
+// the mapping from here.  s0..s2: closure corner of the first patch (node indices); first: index of
+// that patch along x0 inside the colour; count: patches of the workgroup (1..PPW).
+struct ColourBlock {
+  long long s0, s1, s2;
+  int first, count;
+};
+template <int D, int K, int PPW>
+__host__ __device__ inline ColourBlock colour_block(unsigned blk, int p0, int p1, int p2, int cnt0, int cnt1,
+                                                    int groups0) {
+  const int g0 = blk % groups0;
+  const int rest = blk / groups0;
+  const int t1 = rest % cnt1;
+  const int t2 = D == 3 ? rest / cnt1 : 0;
+  ColourBlock cb;
+  cb.first = g0 * PPW;
+  cb.count = cnt0 - cb.first < PPW ? cnt0 - cb.first : PPW;
+  cb.s0 = (long long)K * (p0 + 2 * cb.first);
+  cb.s1 = (long long)K * (p1 + 2 * t1);
+  cb.s2 = D == 3 ? (long long)K * (p2 + 2 * t2) : 0;
+  return cb;
+}
+
 // Round-robin XCD dispatch on MI355X: consecutive workgroup ids land on
 // consecutive XCDs (8 of them).  Remap so that each XCD receives a contiguous
 // run of logical tiles, which keeps neighbouring tiles (sharing faces) in the

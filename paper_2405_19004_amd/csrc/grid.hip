@@ -25,6 +25,7 @@
 // All kernels here write interior nodes only; boundary entries of outputs are
 // zeroed by zero_boundary_kernel where the caller needs it.
 #include <mutex>
+#include <string>
 
 #include "device_common.hpp"
 #include "patch_tables_gen.hpp"
@@ -983,11 +984,21 @@ hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, vo
   return hipGetLastError();
 }
 
+// The tile kernel indexes with 64-bit node offsets; its grid (and tiles0 * tiles1 in int) must fit.
+template <int D, int K>
+bool op_tile_fits(const LevelGeom& g) {
+  using S = OpShape<D, K>;
+  const long long t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1),
+                  t2 = D == 3 ? ceil_div(g.ncells, S::C2) : 1;
+  return t0 * t1 <= 0x7fffffffLL && t0 * t1 * t2 <= 0x7fffffffLL;
+}
+
 template <int D, int K, typename T>
 hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
   using S = OpShape<D, K>;
   const int t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1), t2 = D == 3 ? ceil_div(g.ncells, S::C2) : 1;
   const long long blocks = (long long)t0 * t1 * t2;
+  if (!op_tile_fits<D, K>(g)) return hipErrorInvalidConfiguration;
   const T scale = (T)(D == 3 ? g.h : 1.0);  // A_h = h^(d-2) A_1
   if (b)
     hipLaunchKernelGGL((op_tile_kernel<D, K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
@@ -1015,6 +1026,13 @@ hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, 
   }
 }
 
+template <int D, int K>
+bool pro_fits(const LevelGeom& fine) {
+  using S = ProShape<D, K>;
+  const long long tiles = ceil_div(fine.ncells / 2, S::C);
+  return tiles <= 0x7fffffffLL && tiles * tiles * (D == 3 ? tiles : 1) <= 0x7fffffffLL;
+}
+
 template <int D, int K, typename T>
 hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_t st) {
   using S = ProShape<D, K>;
@@ -1022,7 +1040,7 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
   const int tiles = ceil_div(ncc, S::C);
   const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
   const long long n1dc = (long long)K * ncc + 1;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (!pro_fits<D, K>(fine)) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((prolong_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf,
                      n1dc, fine.n1d, tiles);
   return hipGetLastError();
@@ -1030,30 +1048,40 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
 
 // 3D: in-plane reduction of every fine plane, then the x2 reduction (scratch t: nf x nc x nc).
 // 2D: x0 pass into t (nf x nc), then the x1 pass.
+// The restriction's launch limits: 32-bit offsets inside the plane pass's group of fine planes and
+// inside a coarse plane of the intermediate, grid dimensions y and z below 2^16, grids below 2^31.
+template <int D, int K, typename T>
+bool res_fits(const LevelGeom& fine) {
+  const long long nf = fine.n1d, nc = K * (fine.ncells / 2) + 1, ncc = (nc - 1) / K;
+  if (nf > 0x7fffffffLL) return false;
+  if (D == 3) {
+    using S = ResPlane<K, T>;
+    const long long tiles = ceil_div(nc - 1, S::TX), groups = ceil_div(nf - 2, S::GP);
+    return tiles * tiles <= 0x7fffffffLL && groups <= 65535 && S::GP * nf * nf * (long long)sizeof(T) < (1LL << 31) &&
+           nc <= 65535 && ncc <= 65535 && nc * nc * (long long)sizeof(T) < (1LL << 32) &&
+           ceil_div(ncc, kResCellsPerThread) <= 65535;
+  }
+  return (ncc + 1) * nf / 256 < (1LL << 31) && nc * nc / 256 < (1LL << 31);
+}
+
 template <int D, int K, typename T>
 hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream_t st, void* t, void* xz) {
   const int nf = (int)fine.n1d, nc = (int)(K * (fine.ncells / 2) + 1);
   const int ncc = (nc - 1) / K;
+  if (!res_fits<D, K, T>(fine)) return hipErrorInvalidConfiguration;
   if (D == 3) {
     using S = ResPlane<K, T>;
     // tiles cover coarse columns 0 .. nc - 2: the x2 pass writes 0 on the last column and row
     // whatever the plane values there are
     const int tiles = ceil_div(nc - 1, S::TX);
     const int groups = ceil_div(nf - 2, S::GP);
-    if ((long long)tiles * tiles > 0x7fffffffLL || groups > 65535 ||
-        (long long)S::GP * nf * nf * (long long)sizeof(T) >= (1LL << 31))
-      return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((restrict_plane_kernel<K, T>), dim3((unsigned)(tiles * tiles), (unsigned)groups), dim3(S::NT),
                        0, st, (const T*)rf, (T*)t, (long long)nf, (long long)nc, tiles);
-    if (nc > 65535 || ncc > 65535 || (long long)nc * nc * (long long)sizeof(T) >= (1LL << 32))
-      return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((restrict_z_kernel<K, T>), dim3((unsigned)((nc + 63) / 64), (unsigned)((nc + 3) / 4),
                                                       (unsigned)ceil_div(ncc, kResCellsPerThread)),
                        dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, (T*)xz);
   } else {
     // grid x: 256-thread blocks over one output plane (rows flattened)
-    if ((long long)(ncc + 1) * nf / 256 >= (1LL << 31) || (long long)nc * nc / 256 >= (1LL << 31))
-      return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((restrict_x0_kernel<K, T>), dim3((unsigned)(((long long)(ncc + 1) * nf + 255) / 256)), dim3(256),
                        0, st, (const T*)rf, (T*)t, nf, nc, nf, 1);
     hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), dim3((unsigned)(((long long)nc * nc + 255) / 256)), dim3(256),
@@ -1103,6 +1131,60 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
     }                                                                                    \
     return hipErrorInvalidValue;                                                         \
   } while (0)
+
+namespace {
+
+// Every operator and transfer launch the library issues on level g in precision T is accepted by
+// its launcher: grids within their limits, the kernels' 32-bit offsets valid, tiles and chunks
+// covering the level.
+template <int D, int K, typename T>
+bool grid_launches_ok(const LevelGeom& g, std::string* why) {
+  const std::string tag = std::string(sizeof(T) == 8 ? "FP64 " : "FP32 ");
+  if (D == 3 && g.ncells >= kOpStreamMinCells && op_stream_fits<K, T>(g)) {
+    using S = OpStream<K>;
+    int t0 = 0, cz = 0;
+    const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
+    const long long tiles = (long long)t0 * t0, chunks = tiles > 0 ? blocks / tiles : 0;
+    if (blocks > 0x7fffffffLL) return *why = tag + "streaming operator: grid too large", false;
+    if ((long long)t0 * S::CX < g.ncells || chunks * cz < g.ncells)
+      return *why = tag + "streaming operator: tiles or chunks do not cover the level", false;
+  } else if (!op_tile_fits<D, K>(g)) {
+    return *why = tag + "operator tiles: grid too large", false;
+  }
+  if (g.level >= 2) {
+    if (!res_fits<D, K, T>(g)) return *why = tag + "restriction: launch limits exceeded", false;
+    if (!pro_fits<D, K>(g)) return *why = tag + "prolongation: grid too large", false;
+  }
+  return true;
+}
+
+template <int D, int K>
+bool grid_launches_both(const LevelGeom& g, std::string* why) {
+  return grid_launches_ok<D, K, double>(g, why) && grid_launches_ok<D, K, float>(g, why);
+}
+
+}  // namespace
+
+bool check_grid_launches(const LevelGeom& g, std::string* why) {
+  switch (g.dim * 10 + g.k) {
+    case 21: return grid_launches_both<2, 1>(g, why);
+    case 22: return grid_launches_both<2, 2>(g, why);
+    case 23: return grid_launches_both<2, 3>(g, why);
+    case 24: return grid_launches_both<2, 4>(g, why);
+    case 25: return grid_launches_both<2, 5>(g, why);
+    case 26: return grid_launches_both<2, 6>(g, why);
+    case 27: return grid_launches_both<2, 7>(g, why);
+    case 31: return grid_launches_both<3, 1>(g, why);
+    case 32: return grid_launches_both<3, 2>(g, why);
+    case 33: return grid_launches_both<3, 3>(g, why);
+    case 34: return grid_launches_both<3, 4>(g, why);
+    case 35: return grid_launches_both<3, 5>(g, why);
+    case 36: return grid_launches_both<3, 6>(g, why);
+    case 37: return grid_launches_both<3, 7>(g, why);
+  }
+  *why = "unsupported (dim, degree)";
+  return false;
+}
 
 hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b, void* y, hipStream_t st) {
   VPS_DISPATCH(op_launch, g, prec, x, b, y, st);

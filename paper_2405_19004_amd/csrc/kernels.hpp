@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include "device_common.hpp"
 
 namespace vps {
@@ -79,6 +81,12 @@ hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e,
 // The allocation-free restriction's scratch: a static device array of noalloc_scratch_bytes()
 // bytes per GPU.  noalloc_scratch() returns its device address on the current device (looked up
 // once per device and kept).
+// Host-side launch geometry of one level (no device work): every colour-pass workgroup of every
+// colour and launch shape maps to patches of that colour inside the grid, covers each patch once
+// and stays within the kernels' 32-bit offsets; every operator and transfer launch fits its
+// launcher's limits.  False with a reason otherwise; *blocks adds the workgroups enumerated.
+bool check_colour_launches(const LevelGeom& g, long long* blocks, std::string* why);
+bool check_grid_launches(const LevelGeom& g, std::string* why);
 size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch(void** out);
 hipError_t launch_zero_boundary(const LevelGeom& g, int prec, void* y, hipStream_t st);

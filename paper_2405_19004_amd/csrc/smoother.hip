@@ -233,14 +233,9 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   T* bufA = smem;
   T* bufB = smem + L::A;
 
-  const int g0 = blk % groups0;
-  const int rest = blk / groups0;
-  const int t1 = rest % cnt1, t2 = rest / cnt1;
-  const int tfirst = g0 * PPW;
-  const int P = min(PPW, cnt0 - tfirst);
-  const long long s0 = (long long)K * (p0 + 2 * tfirst);
-  const long long s1 = (long long)K * (p1 + 2 * t1);
-  const long long s2 = (long long)K * (p2 + 2 * t2);
+  const ColourBlock cb = colour_block<3, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
+  const int P = cb.count;
+  const long long s0 = cb.s0, s1 = cb.s1, s2 = cb.s2;
   const long long n1d2 = n1d * n1d;
   const int tid = threadIdx.x;
   const int seg = 2 * K * P + 1;  // valid closure columns along x0
@@ -498,15 +493,9 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   T* bufB = smem + L::offB;
   (void)p2;
 
-  const int g0 = blk % groups0;
-  const int rest = blk / groups0;
-  const int t1 = rest % cnt1;
-  const int t2 = D == 3 ? rest / cnt1 : 0;
-  const int tfirst = g0 * PPW;
-  const int P = min(PPW, cnt0 - tfirst);
-  const long long s0 = (long long)K * (p0 + 2 * tfirst);
-  const long long s1 = (long long)K * (p1 + 2 * t1);
-  const long long s2 = D == 3 ? (long long)K * (p2 + 2 * t2) : 0;
+  const ColourBlock cb = colour_block<D, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
+  const int P = cb.count;
+  const long long s0 = cb.s0, s1 = cb.s1, s2 = cb.s2;
   const long long n1d2 = n1d * n1d;
   const int tid = threadIdx.x;
   const int seg = 2 * K * P + 1;  // valid length of the closure row segment
@@ -1020,14 +1009,9 @@ __device__ __forceinline__ void colour_pass_mfma3(float* __restrict__ smem, cons
   float* const rA = smem;         // X, then U/V, then odd diagonalisation buffers
   float* const rB = smem + L::A;  // PM/PA, then Q, then even ones
 
-  const int g0 = blk % groups0;
-  const int rest = blk / groups0;
-  const int t1 = rest % cnt1, t2 = rest / cnt1;
-  const int tfirst = g0 * PPW;
-  const int P = min(PPW, cnt0 - tfirst);
-  const long long s0 = (long long)K * (p0 + 2 * tfirst);
-  const long long s1 = (long long)K * (p1 + 2 * t1);
-  const long long s2 = (long long)K * (p2 + 2 * t2);
+  const ColourBlock cb = colour_block<3, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
+  const int P = cb.count;
+  const long long s0 = cb.s0, s1 = cb.s1, s2 = cb.s2;
   const long long n1d2 = n1d * n1d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;  // matrix-core row (A) / column (B, D) and input sub-index
@@ -1541,6 +1525,78 @@ hipError_t launch_colour_pass_group(int dim, int k, int prec, int mode, int colo
                                     int n_members, hipStream_t st) {
   return dim == 2 ? group_k<2>(k, prec, mode, colour, members, n_members, st)
                   : group_k<3>(k, prec, mode, colour, members, n_members, st);
+}
+
+// ------------------------------------------------------------ host-side launch geometry
+
+namespace {
+
+// Every workgroup of one colour's launch with PPW patches per workgroup: its patches lie in the
+// colour and inside the grid, the workgroups cover the colour's patches once, and the farthest
+// closure node of a workgroup is within the kernels' 32-bit byte offsets (8-byte words).
+template <int D, int K, int PPW>
+bool colour_shape_ok(const LevelGeom& g, int colour, long long* nblk, std::string* why) {
+  const ColourGrid<D, K> cg(g, colour, PPW);
+  if (cg.blocks == 0) return true;
+  const std::string tag = "colour " + std::to_string(colour) + ", " + std::to_string(PPW) + " patches per workgroup: ";
+  if (!cg.ok) return *why = tag + "launch refused (offsets or grid beyond 32 bits)", false;
+  const long long n1d = g.n1d, nc = g.ncells, span = 2LL * K;
+  long long patches = 0;
+  for (long long b = 0; b < cg.blocks; ++b) {
+    const ColourBlock cb = colour_block<D, K, PPW>((unsigned)b, cg.p[0], cg.p[1], cg.p[2], cg.cnt[0], cg.cnt[1],
+                                                   cg.groups0);
+    if (cb.count < 1 || cb.count > PPW) return *why = tag + "workgroup without patches", false;
+    const long long s[3] = {cb.s0, cb.s1, cb.s2};
+    for (int a = 0; a < D; ++a) {
+      const long long v = s[a] / K + 1;  // vertex of the workgroup's first patch
+      if (s[a] % K != 0 || v < 1 || v > nc - 1 || ((v - 1) & 1) != cg.p[a])
+        return *why = tag + "patch outside the colour", false;
+    }
+    if (s[0] / K + 1 + 2LL * (cb.count - 1) > nc - 1) return *why = tag + "patch past the last vertex", false;
+    if (cb.s0 + span * cb.count > n1d - 1 || cb.s1 + span > n1d - 1 || (D == 3 && cb.s2 + span > n1d - 1))
+      return *why = tag + "closure outside the grid", false;
+    const long long far = (D == 3 ? span * n1d * n1d : 0) + span * n1d + span * cb.count;
+    if (far * 8 >= (1LL << 32)) return *why = tag + "closure offsets beyond 32 bits", false;
+    patches += cb.count;
+  }
+  const long long want = (long long)cg.cnt[0] * cg.cnt[1] * (D == 3 ? cg.cnt[2] : 1);
+  if (patches != want) return *why = tag + "workgroups do not cover the colour once", false;
+  *nblk += cg.blocks;
+  return true;
+}
+
+template <int D, int K>
+bool colour_launches_ok(const LevelGeom& g, long long* nblk, std::string* why) {
+  for (int c = 0; c < (1 << D); ++c) {
+    if (!colour_shape_ok<D, K, SmootherShape<D, K>::PPW>(g, c, nblk, why)) return false;
+    if (!colour_shape_ok<D, K, LatencyPPW<D, K>::value>(g, c, nblk, why)) return false;
+    if constexpr (HasMfmaForm<D, K, float>::value)
+      if (!colour_shape_ok<D, K, kMfmaPPW>(g, c, nblk, why)) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+bool check_colour_launches(const LevelGeom& g, long long* blocks, std::string* why) {
+  switch (g.dim * 10 + g.k) {
+    case 21: return colour_launches_ok<2, 1>(g, blocks, why);
+    case 22: return colour_launches_ok<2, 2>(g, blocks, why);
+    case 23: return colour_launches_ok<2, 3>(g, blocks, why);
+    case 24: return colour_launches_ok<2, 4>(g, blocks, why);
+    case 25: return colour_launches_ok<2, 5>(g, blocks, why);
+    case 26: return colour_launches_ok<2, 6>(g, blocks, why);
+    case 27: return colour_launches_ok<2, 7>(g, blocks, why);
+    case 31: return colour_launches_ok<3, 1>(g, blocks, why);
+    case 32: return colour_launches_ok<3, 2>(g, blocks, why);
+    case 33: return colour_launches_ok<3, 3>(g, blocks, why);
+    case 34: return colour_launches_ok<3, 4>(g, blocks, why);
+    case 35: return colour_launches_ok<3, 5>(g, blocks, why);
+    case 36: return colour_launches_ok<3, 6>(g, blocks, why);
+    case 37: return colour_launches_ok<3, 7>(g, blocks, why);
+  }
+  *why = "unsupported (dim, degree)";
+  return false;
 }
 
 hipError_t init_smoother_tables() {
