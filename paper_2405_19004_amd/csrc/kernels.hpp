@@ -31,7 +31,10 @@ hipError_t init_smoother_tables();
 // (x^I += A_j^{-1} b^I) and Boundary (x^I = A_j^{-1} (b^I - A^{IB} x^B), x^I never read).
 // kModeMfma: the multiplicative pass with the residual contractions on the matrix cores (3D Q4
 // FP32, default launch shape); elsewhere the same as kModeMultiplicative.
-enum { kModeMultiplicative = 0, kModeAdditive = 1, kModeBoundary = 2, kModeMfma = 4 };
+// kModeZero: colour 0 of the multiplicative pass on a zero iterate, x <- S_0(0, b): writes
+// A_j^{-1} b^I on the colour's patch interiors and 0 on every other node (the closures of colour 0
+// tile the grid), so x need not be cleared first and is never read.
+enum { kModeMultiplicative = 0, kModeAdditive = 1, kModeBoundary = 2, kModeMfma = 4, kModeZero = 5 };
 
 // One member of a packed colour-pass launch (see launch_colour_pass_group).
 struct ColourPassDesc {

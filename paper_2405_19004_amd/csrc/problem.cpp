@@ -217,8 +217,9 @@ Status smoother(Problem* p, int level, int prec, int mode, bool reverse, const v
   for (int i = 0; i < nc; ++i) {
     const int c = reverse ? nc - 1 - i : i;
     // on x = 0 the first multiplicative colour reduces to x^I = A_j^{-1} b^I (residual = b,
-    // x^B = 0): the additive kernel gives the same values without forming the residual
-    const int m = (i == 0 && x_zero && mode != kModeAdditive) ? kModeAdditive : mode;
+    // x^B = 0): the additive kernel gives the same values without forming the residual; for colour
+    // 0 the from-zero kernel also writes the zeros of the rest of the grid, so x may hold anything
+    const int m = (i == 0 && x_zero && mode != kModeAdditive) ? (c == 0 ? kModeZero : kModeAdditive) : mode;
     VPS_TRY(colour_pass(p, level, prec, m, c, b, x));
   }
   return Status::ok();
@@ -374,7 +375,7 @@ Status vcycle_group(Problem* const* ps, int n, int prec, const void* const* bL, 
       if (ps[i]->L >= lvl) mem.push_back({ps[i]->geom(lvl), level_b(i, lvl), level_x(i, lvl)});
     for (int j = 0; j < nc; ++j) {
       const int c = reverse ? nc - 1 - j : j;
-      int mode = (j == 0 && x_zero) ? kModeAdditive : vcycle_mode(ps[0]);
+      int mode = (j == 0 && x_zero) ? (c == 0 ? kModeZero : kModeAdditive) : vcycle_mode(ps[0]);
       if (mode == kSmoothSeparate) {
         // residual of every member, then the packed local solves on it
         sep.assign(mem.begin(), mem.end());
@@ -427,14 +428,14 @@ const float* cg_z32(const Problem* p, int mode) {
 // result in the level-L FP32 iterate (cg_z32): its consumers widen it exactly as they read it.
 Status precondition_launch(Problem* p, int mode) {
   const long long N = p->lv[p->L].N;
+  // z = V(r) from z = 0: the V-cycle's first pass (colour 0 from zero, or the coarse solve on a
+  // one-level hierarchy) writes every node of z, so z is not cleared first
   if (mode == 0) {
-    VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
     VPS_TRY(vcycle_top(p, 0, p->L, p->r, p->z, true));
     VPS_HIP(launch_dot2(p->r, p->z, nullptr, nullptr, N, p->partial, p->sc + kScRZNew, p->stream));
     return Status::ok();
   }
   LevelBuffers& B = p->lv[p->L];
-  VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
   VPS_TRY(vcycle_top(p, 1, p->L, B.b[1], B.x[1], true));
   VPS_HIP(launch_dot_rz32((const float*)B.x[1], p->r, N, p->partial, p->sc + kScRZNew, p->stream));
   return Status::ok();
@@ -494,13 +495,13 @@ Status precondition_group(Problem* const* ps, int n, int mode) {
   for (int i = 0; i < n; ++i) {
     Problem* p = ps[i];
     const long long N = p->lv[p->L].N;
+    // x = 0 on entry without a fill: the first colour pass of the group's V-cycle (from zero)
+    // writes every node
     if (mode == 0) {
-      VPS_HIP(launch_fill(0, p->z, N, 0.0, p->stream));
       bs[i] = p->r;
       xs[i] = p->z;
     } else {
       LevelBuffers& B = p->lv[p->L];
-      VPS_HIP(launch_fill(1, B.x[1], N, 0.0, p->stream));
       bs[i] = B.b[1];
       xs[i] = B.x[1];
     }

@@ -484,7 +484,9 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
                                                   int groups0, T res_scale, T sol_scale, unsigned blk) {
   constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
   constexpr int NT = SmootherShape<D, K>::NT;
-  constexpr bool ADD = MODE == kModeAdditive, BND = MODE == kModeBoundary;
+  // ZERO: the additive pass on x = 0 that also writes the zeros of the rest of its closures
+  constexpr bool ZERO = MODE == kModeZero;
+  constexpr bool ADD = MODE == kModeAdditive || ZERO, BND = MODE == kModeBoundary;
   // patch matrices and eigenvectors as compile-time constants (instruction literals / SGPR moves)
   using PT = gen::PatchTables<T, K>;
   using L = SmootherLds<D, K, T, ADD, PPW>;
@@ -536,9 +538,26 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
     const int st = D == 3 ? ld2 : ld1;
 #pragma unroll
     for (int i = 0; i < m; ++i) bpre[rr][i] = ld_lane(bo + st + i * st, loff[rr]);
-    if constexpr (ADD) {
+    if constexpr (ADD && !ZERO) {
 #pragma unroll
       for (int i = 0; i < m; ++i) xpre[rr][i] = ld_lane(xo + st + i * st, loff[rr]);
+    }
+    if constexpr (ZERO) {
+#pragma unroll
+      for (int i = 0; i < m; ++i) xpre[rr][i] = T(0);
+    }
+  }
+
+  if constexpr (ZERO) {
+    // 0 on every closure node of the workgroup that is not a patch interior (neighbouring
+    // workgroups write the same zeros on shared faces; no interior of the colour lies there)
+    constexpr int NZ = D == 3 ? n * n * RS : n * RS;
+    for (int w = tid; w < NZ; w += NT) {
+      const int c = w % RS, r = w / RS;  // r = j2 * n + j1 (3D) or j1 (2D)
+      const int j1 = D == 3 ? r % n : r, j2 = D == 3 ? r / n : 0;
+      const bool inner = c % (2 * K) != 0 && j1 > 0 && j1 < n - 1 && (D == 2 || (j2 > 0 && j2 < n - 1));
+      if (c < seg && !inner)
+        st_lane(xo, (unsigned)((D == 3 ? j2 * ld2 : 0) + j1 * ld1 + c) * (unsigned)sizeof(T), T(0));
     }
   }
 
@@ -1289,7 +1308,7 @@ struct ColourLds {
   static constexpr bool kMult3 = D == 3 && MODE == kModeMultiplicative && sizeof(T) == 8;
   static constexpr int value = kMfma ? MfmaLds<K, PPW>::total
                                : kMult3 ? Mult3Lds<K, PPW>::total
-                                        : SmootherLds<D, K, T, MODE == kModeAdditive, PPW>::total;
+                                        : SmootherLds<D, K, T, MODE == kModeAdditive || MODE == kModeZero, PPW>::total;
 };
 
 // One workgroup's share of a colour pass: the 3D multiplicative pass in FP64 contracts the closure
@@ -1456,6 +1475,9 @@ static hipError_t dispatch_mode(const LevelGeom& g, int mode, int colour, const 
     case kModeMfma:
       if constexpr (HasMfmaForm<D, K, T>::value) return launch_one<D, K, T, kModeMfma>(g, colour, b, x, st);
       return launch_one<D, K, T, kModeMultiplicative>(g, colour, b, x, st);
+    case kModeZero:
+      if (colour != 0) return hipErrorInvalidValue;  // only colour 0's closures tile the grid
+      return launch_one<D, K, T, kModeZero>(g, colour, b, x, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1498,6 +1520,11 @@ static hipError_t group_prec(int prec, int mode, int colour, const ColourPassMem
   if (mode == kModeBoundary)
     return prec == 0 ? launch_group<D, K, double, kModeBoundary>(colour, m, nm, st)
                      : launch_group<D, K, float, kModeBoundary>(colour, m, nm, st);
+  if (mode == kModeZero) {
+    if (colour != 0) return hipErrorInvalidValue;
+    return prec == 0 ? launch_group<D, K, double, kModeZero>(colour, m, nm, st)
+                     : launch_group<D, K, float, kModeZero>(colour, m, nm, st);
+  }
   if (mode == kModeMfma) {
     if constexpr (HasMfmaForm<D, K, float>::value)
       if (prec == 1) return launch_group<D, K, float, kModeMfma>(colour, m, nm, st);
