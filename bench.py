@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--no-table7", action="store_true",
                     help="skip the mixed/double solves at the sizes of Table 7 (135M-721M DoFs)")
     ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the closed-loop mixed serving run of --serve requests (for profiling)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only 8 FP32 and 8 FP64 colour passes on the finest level, twice (for counter runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -135,7 +137,7 @@ def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def serving_run(v, n_requests, max_active=16, budget=64 << 30):
+def serving_run(v, n_requests, max_active=16, budget=64 << 30, closed_loop_only=False):
     """Continuous-batching server over a seeded stream of mixed (d, k, level) requests.
 
     Right-hand sides are assembled on the device before the clock starts.  First a closed-loop
@@ -216,6 +218,9 @@ def serving_run(v, n_requests, max_active=16, budget=64 << 30):
 
     total = sum(sizes)
     closed = run(0.0)
+    if closed_loop_only:
+        return {"requests": len(trace), "total_dofs": total, "max_active": max_active,
+                "closed_loop_mixed": summary(*closed)}
     capacity = len(trace) / closed[0]
     rate = 0.8 * capacity
     res = {"requests": len(trace), "total_dofs": total, "max_active": max_active, "arrival_rate_per_s": rate}
@@ -396,6 +401,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 4}))
+        return
+    if a.serve_only:
+        print(json.dumps(serving_run(v, a.serve, closed_loop_only=True)))
         return
     FL = v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY
     P = v.Problem(D, K, L, FL | v.VPS_FLAG_POST_SAME_ORDER)
