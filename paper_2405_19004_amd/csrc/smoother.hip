@@ -55,9 +55,17 @@ template <int K> struct SmootherShape<2, K> {
 #ifndef VPS_Q4_3D_NT
 #define VPS_Q4_3D_NT 128
 #endif
+// Degrees (bit K) whose default 3D shape takes the aliased LDS layout: measured 2-13% faster for
+// degrees 3-7 (occupancy), no gain for degrees 1-2, where the layout is already small.
+#ifndef VPS_3D_ALIAS_MASK
+#define VPS_3D_ALIAS_MASK 0xF8
+#endif
 template <int K> struct SmootherShape<3, K> {
   static constexpr int PPW = K == 1 ? 32 : K == 2 ? 8 : K == 3 ? 4 : K == 4 ? VPS_Q4_3D_PPW : 1;
   static constexpr int NT = K == 4 ? VPS_Q4_3D_NT : K <= 5 ? 128 : K == 6 ? 192 : 256;
+  // the default shape of the multiplicative pass shares one LDS region between the closure and the
+  // first two contraction stages (see SmootherLds)
+  static constexpr bool ALIAS = ((VPS_3D_ALIAS_MASK) >> K) & 1;
 };
 
 // Patches per workgroup for small launches (coarse levels): fewer patches per workgroup means
@@ -78,7 +86,7 @@ constexpr int pad32(int v, int r) { return v + ((r - v) % 32 + 32) % 32; }
 // LDS layouts.  Every transpose buffer puts the loop axis of the stage that reads it outermost,
 // so the reading lanes touch consecutive words; the outer stride is padded (mod 32) so that the
 // writing lanes of the previous stage also fall into distinct banks.
-template <int D, int K, typename T, bool ADD, int PPWv>
+template <int D, int K, typename T, bool ADD, int PPWv, bool ALIASv = false>
 struct SmootherLds {
   static constexpr int n = 2 * K + 1, m = 2 * K - 1;
   static constexpr int PPW = PPWv;
@@ -108,9 +116,18 @@ struct SmootherLds {
   static constexpr int P2 = ADD ? 0 : 2 * n * T1;
   static constexpr int A2 = P2 > m * TA ? P2 : m * TA;
   static constexpr int B2 = X2 > m * T0 ? X2 : m * T0;
-  static constexpr int total = D == 3 ? A3 + B3 : A2 + B2;
+  // ---- aliased 3D layout (multiplicative): the closure X, PM/PA and U/V all start at word 0 (the x0
+  // and x1 stages read their inputs into registers and the workgroup synchronises before they
+  // write), the x2 and x0 diagonalisation outputs (W4, W6) follow U/V, the x1 ones (W5, W7) start
+  // at 0 again once U/V is dead
+  static constexpr bool AL = ALIASv && D == 3 && !ADD;
+  static constexpr int W46 = m * SI1 > m * SA1 ? m * SI1 : m * SA1;
+  static constexpr int AL3a = X3 > P3 ? X3 : P3;
+  static constexpr int AL3 = AL3a > UV3 + W46 ? AL3a : UV3 + W46;
+  static constexpr int total = D == 3 ? (AL ? AL3 : A3 + B3) : A2 + B2;
   static constexpr int offA = 0;
-  static constexpr int offB = D == 3 ? A3 : A2;
+  static constexpr int offB = D == 3 ? (AL ? 0 : A3) : A2;
+  static constexpr int offW = AL ? UV3 : 0;  // W4 and W6 (the other buffers use offA and offB)
 };
 
 __device__ __forceinline__ bool on_boundary(long long i, long long n1d) { return i == 0 || i == n1d - 1; }
@@ -476,6 +493,14 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   }
 }
 
+// The aliased LDS layout serves the default shape of the 3D multiplicative pass where the shape
+// asks for it.
+template <int D, int K, int MODE, int PPW>
+struct LinesAlias {
+  static constexpr bool value =
+      D == 3 && MODE == kModeMultiplicative && SmootherShape<3, K>::ALIAS && PPW == SmootherShape<3, K>::PPW;
+};
+
 // One workgroup's share of a colour pass: patches of block `blk` of the colour described by
 // (p0, p1, p2, cnt0, cnt1, groups0) on a level with n1d nodes per direction.
 template <int D, int K, typename T, int MODE, int PPW>
@@ -489,10 +514,11 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   constexpr bool ADD = MODE == kModeAdditive || ZERO, BND = MODE == kModeBoundary;
   // patch matrices and eigenvectors as compile-time constants (instruction literals / SGPR moves)
   using PT = gen::PatchTables<T, K>;
-  using L = SmootherLds<D, K, T, ADD, PPW>;
+  using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, MODE, PPW>::value>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
+  T* bufW = smem + L::offW;
   (void)p2;
 
   const ColourBlock cb = colour_block<D, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
@@ -676,6 +702,48 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
             }
           }
         }
+      } else if constexpr (L::AL) {
+        // aliased: every line of the workgroup is read and contracted, then PM/PA overwrite X
+        constexpr int NA = PPW * n * n, RA = (NA + NT - 1) / NT;
+        T om[RA][m], oa[RA][m];
+#pragma unroll
+        for (int rr = 0; rr < RA; ++rr) {
+          const int task = rr * NT + tid;
+          const int q = task / (n * n), r = task - q * (n * n);
+          const int j2 = r / n, j1 = r - j2 * n;
+          if (task < NA && q < P) {
+            T in[n];
+            const int row = lds_base((j2 * n + j1) * RS + 2 * K * q);
+#pragma unroll
+            for (int j = 0; j < n; ++j) in[j] = X[row + j];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              T sm = T(0), sa = T(0);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
+                sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
+              }
+              om[rr][i] = sm;
+              oa[rr][i] = sa;
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < RA; ++rr) {
+          const int task = rr * NT + tid;
+          const int q = task / (n * n), r = task - q * (n * n);
+          const int j2 = r / n, j1 = r - j2 * n;
+          if (task < NA && q < P) {
+            const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              PM[o + i] = om[rr][i];
+              PA[o + i] = oa[rr][i];
+            }
+          }
+        }
       } else
       for (int base = 0; base < PPW * n * n; base += NT) {
         const int task = base + tid;
@@ -707,6 +775,51 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
       // ---- contract x1: lines (q, j2, i0), i0 fastest; U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)
       T* U = bufB;  // [j2][q][i1][i0]
       T* V = bufB + n * SJ2;
+      if constexpr (L::AL) {
+        // aliased: U/V overwrite PM/PA once every line has been read
+        constexpr int NB2 = PPW * n * m, RB2 = (NB2 + NT - 1) / NT;
+        T ou[RB2][m], ov[RB2][m];
+#pragma unroll
+        for (int rr = 0; rr < RB2; ++rr) {
+          const int task = rr * NT + tid;
+          const int q = task / (n * m);
+          if (task < NB2 && q < P) {
+            T pm[n], pa[n];
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+              pm[j] = PM[j * SJ1 + task];
+              pa[j] = PA[j * SJ1 + task];
+            }
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              T su = T(0), sv = T(0);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                su = fma_tab(PT::Mc[i * n + j], pm[j], su);
+                sv = fma_tab(PT::Ac[i * n + j], pm[j], sv);
+                sv = fma_tab(PT::Mc[i * n + j], pa[j], sv);
+              }
+              ou[rr][i] = su;
+              ov[rr][i] = sv;
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < RB2; ++rr) {
+          const int task = rr * NT + tid;
+          const int q = task / (n * m), r = task - q * (n * m);
+          const int j2 = r / m, i0 = r - j2 * m;
+          if (task < NB2 && q < P) {
+            const int o = lds_base(j2 * SJ2 + q * mm + i0);
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              U[o + i * m] = ou[rr][i];
+              V[o + i * m] = ov[rr][i];
+            }
+          }
+        }
+      } else
       for (int base = 0; base < PPW * n * m; base += NT) {
         const int task = base + tid;
         const int q = task / (n * m), r = task - q * (n * m);
@@ -737,7 +850,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
       __syncthreads();
     }
     // ---- contract x2 (residual) and apply Sᵀ along x2: lines (q, i1, i0), i0 fastest
-    T* W4 = bufA;  // [i1][q][a2][i0]
+    T* W4 = bufW;  // [i1][q][a2][i0]
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int task = rr * NT + tid;
@@ -795,7 +908,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
     }
     __syncthreads();
     // ---- Sᵀ along x0, scale by 1/(lam2+lam1+lam0), S along x0: lines (q, a2, a1), a1 fastest
-    T* W6 = bufA;  // [a1][q][a2][i0]
+    T* W6 = bufW;  // [a1][q][a2][i0]
     for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
       const int q = task / mm, r = task - q * mm;
@@ -1308,7 +1421,8 @@ struct ColourLds {
   static constexpr bool kMult3 = D == 3 && MODE == kModeMultiplicative && sizeof(T) == 8;
   static constexpr int value = kMfma ? MfmaLds<K, PPW>::total
                                : kMult3 ? Mult3Lds<K, PPW>::total
-                                        : SmootherLds<D, K, T, MODE == kModeAdditive || MODE == kModeZero, PPW>::total;
+                                        : SmootherLds<D, K, T, MODE == kModeAdditive || MODE == kModeZero, PPW,
+                                                      LinesAlias<D, K, MODE, PPW>::value>::total;
 };
 
 // One workgroup's share of a colour pass: the 3D multiplicative pass in FP64 contracts the closure
