@@ -493,12 +493,32 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   }
 }
 
+// Wide shape of the 3D Q4 FP32 multiplicative pass: five patches per workgroup on 256 threads.
+// Its 49-line stages fill 245 of 256 lanes, against 98 of 128 for the two-patch default, which
+// cuts the vector instructions per patch by about a fifth.  A row of patches along x0 that is not
+// a multiple of five leaves a partial workgroup, so launches take it only on long rows (at most
+// kWideIdle idle patch slots per row, as a fraction of the row).
+#ifndef VPS_Q4_3D_WIDE
+#define VPS_Q4_3D_WIDE 1
+#endif
+constexpr int kWidePPW = 5, kWideNT = 256;
+constexpr double kWideIdle = 0.15;
+template <int D, int K, typename T, int MODE>
+struct HasWideForm {
+  static constexpr bool value = D == 3 && K == 4 && sizeof(T) == 4 && MODE == kModeMultiplicative && VPS_Q4_3D_WIDE;
+};
+template <int D, int K, typename T, int MODE, int PPW>
+struct IsWide {
+  static constexpr bool value = HasWideForm<D, K, T, MODE>::value && PPW == kWidePPW;
+};
+
 // The aliased LDS layout serves the default shape of the 3D multiplicative pass where the shape
-// asks for it.
-template <int D, int K, int MODE, int PPW>
+// asks for it, and the wide shape.
+template <int D, int K, typename T, int MODE, int PPW>
 struct LinesAlias {
   static constexpr bool value =
-      D == 3 && MODE == kModeMultiplicative && SmootherShape<3, K>::ALIAS && PPW == SmootherShape<3, K>::PPW;
+      (D == 3 && MODE == kModeMultiplicative && SmootherShape<3, K>::ALIAS && PPW == SmootherShape<3, K>::PPW) ||
+      IsWide<D, K, T, MODE, PPW>::value;
 };
 
 // One workgroup's share of a colour pass: patches of block `blk` of the colour described by
@@ -508,13 +528,13 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
                                                   long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
                                                   int groups0, T res_scale, T sol_scale, unsigned blk) {
   constexpr int n = 2 * K + 1, m = 2 * K - 1, mm = m * m;
-  constexpr int NT = SmootherShape<D, K>::NT;
+  constexpr int NT = IsWide<D, K, T, MODE, PPW>::value ? kWideNT : SmootherShape<D, K>::NT;
   // ZERO: the additive pass on x = 0 that also writes the zeros of the rest of its closures
   constexpr bool ZERO = MODE == kModeZero;
   constexpr bool ADD = MODE == kModeAdditive || ZERO, BND = MODE == kModeBoundary;
   // patch matrices and eigenvectors as compile-time constants (instruction literals / SGPR moves)
   using PT = gen::PatchTables<T, K>;
-  using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, MODE, PPW>::value>;
+  using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, T, MODE, PPW>::value>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
@@ -1412,7 +1432,9 @@ struct ColourShape {
 // latency shape).
 template <int D, int K, typename T, int MODE, int PPW>
 struct ColourNT {
-  static constexpr int value = UsesMfma<D, K, T, MODE>::value && PPW == kMfmaPPW ? 256 : SmootherShape<D, K>::NT;
+  static constexpr int value = UsesMfma<D, K, T, MODE>::value && PPW == kMfmaPPW ? 256
+                               : IsWide<D, K, T, MODE, PPW>::value               ? kWideNT
+                                                                                 : SmootherShape<D, K>::NT;
 };
 
 template <int D, int K, typename T, int MODE, int PPW>
@@ -1422,7 +1444,7 @@ struct ColourLds {
   static constexpr int value = kMfma ? MfmaLds<K, PPW>::total
                                : kMult3 ? Mult3Lds<K, PPW>::total
                                         : SmootherLds<D, K, T, MODE == kModeAdditive || MODE == kModeZero, PPW,
-                                                      LinesAlias<D, K, MODE, PPW>::value>::total;
+                                                      LinesAlias<D, K, T, MODE, PPW>::value>::total;
 };
 
 // One workgroup's share of a colour pass: the 3D multiplicative pass in FP64 contracts the closure
@@ -1500,9 +1522,21 @@ static hipError_t launch_shape(const LevelGeom& g, const ColourGrid<D, K>& cg, c
   return hipGetLastError();
 }
 
+// The wide shape's launch: enough workgroups to leave the small-launch regime and few idle patch
+// slots at row ends.
+template <int D, int K>
+static bool wide_fits(const ColourGrid<D, K>& cw) {
+  return cw.ok && cw.blocks >= kLatencyBlocks &&
+         (double)(cw.groups0 * kWidePPW - cw.cnt[0]) <= kWideIdle * (double)cw.cnt[0];
+}
+
 template <int D, int K, typename T, int MODE>
 static hipError_t launch_one(const LevelGeom& g, int colour, const void* b, void* x, hipStream_t st) {
   constexpr int PPW = ColourShape<D, K, T, MODE>::PPW, LPPW = LatencyPPW<D, K>::value;
+  if constexpr (HasWideForm<D, K, T, MODE>::value) {
+    const ColourGrid<D, K> cw(g, colour, kWidePPW);
+    if (wide_fits(cw)) return launch_shape<D, K, T, MODE, kWidePPW>(g, cw, b, x, st);
+  }
   const ColourGrid<D, K> cg(g, colour, PPW);
   if (!cg.ok) return hipErrorInvalidConfiguration;
   if (cg.blocks == 0) return hipSuccess;
@@ -1713,6 +1747,8 @@ bool colour_launches_ok(const LevelGeom& g, long long* nblk, std::string* why) {
     if (!colour_shape_ok<D, K, LatencyPPW<D, K>::value>(g, c, nblk, why)) return false;
     if constexpr (HasMfmaForm<D, K, float>::value)
       if (!colour_shape_ok<D, K, kMfmaPPW>(g, c, nblk, why)) return false;
+    if constexpr (HasWideForm<D, K, float, kModeMultiplicative>::value)
+      if (!colour_shape_ok<D, K, kWidePPW>(g, c, nblk, why)) return false;
   }
   return true;
 }
