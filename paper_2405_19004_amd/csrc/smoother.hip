@@ -80,13 +80,25 @@ struct LatencyPPW {
 #endif
 constexpr long long kLatencyBlocks = VPS_LATENCY_BLOCKS;
 
+// Two words of T moved by one 8- or 16-byte LDS access.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+
 // Smallest s >= v with s = r (mod 32): padded outer strides of the LDS transpose buffers.
 constexpr int pad32(int v, int r) { return v + ((r - v) % 32 + 32) % 32; }
 
 // LDS layouts.  Every transpose buffer puts the loop axis of the stage that reads it outermost,
 // so the reading lanes touch consecutive words; the outer stride is padded (mod 32) so that the
 // writing lanes of the previous stage also fall into distinct banks.
-template <int D, int K, typename T, bool ADD, int PPWv, bool ALIASv = false>
+template <int D, int K, typename T, bool ADD, int PPWv, bool ALIASv = false, bool PAIRv = false>
 struct SmootherLds {
   static constexpr int n = 2 * K + 1, m = 2 * K - 1;
   static constexpr int PPW = PPWv;
@@ -122,12 +134,28 @@ struct SmootherLds {
   // at 0 again once U/V is dead
   static constexpr bool AL = ALIASv && D == 3 && !ADD;
   static constexpr int W46 = m * SI1 > m * SA1 ? m * SI1 : m * SA1;
+  static constexpr int W57 = m * SI0 > m * SA2 ? m * SI0 : m * SA2;
   static constexpr int AL3a = X3 > P3 ? X3 : P3;
   static constexpr int AL3 = AL3a > UV3 + W46 ? AL3a : UV3 + W46;
-  static constexpr int total = D == 3 ? (AL ? AL3 : A3 + B3) : A2 + B2;
+  // ---- paired 3D layout (aliased, smaller still): PM and PA interleaved as pairs [j1][q][j2][i0]{M, A}
+  // (one 8-byte access per pair, the pair stride SJP padded for conflict-free writes of the x0
+  // stage), W4 also over U/V (the x2 stage synchronises before it writes), W5 and W7 after W4/W6
+  static constexpr bool PR = PAIRv && AL;
+  static constexpr int SJP = pad32(2 * PPW * n * m, 30);
+  static constexpr int PP3 = ADD ? 0 : n * SJP;
+  static constexpr int PR3a = X3 > PP3 ? X3 : PP3;
+  static constexpr int PR3b = UV3 > W46 + W57 ? UV3 : W46 + W57;
+  static constexpr int PR3 = PR3a > PR3b ? PR3a : PR3b;
+  static constexpr int total = D == 3 ? (PR ? PR3 : AL ? AL3 : A3 + B3) : A2 + B2;
+  // 2D: PM/PA and the diagonalisation buffers at offA, the closure and W at offB
   static constexpr int offA = 0;
   static constexpr int offB = D == 3 ? (AL ? 0 : A3) : A2;
-  static constexpr int offW = AL ? UV3 : 0;  // W4 and W6 (the other buffers use offA and offB)
+  // 3D buffers
+  static constexpr int offX = AL ? 0 : A3;
+  static constexpr int offP = 0;
+  static constexpr int offUV = AL ? 0 : A3;
+  static constexpr int offW46 = PR ? 0 : AL ? UV3 : 0;  // W4 and W6
+  static constexpr int offW57 = PR ? W46 : AL ? 0 : A3;  // W5 and W7
 };
 
 __device__ __forceinline__ bool on_boundary(long long i, long long n1d) { return i == 0 || i == n1d - 1; }
@@ -534,11 +562,10 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   constexpr bool ADD = MODE == kModeAdditive || ZERO, BND = MODE == kModeBoundary;
   // patch matrices and eigenvectors as compile-time constants (instruction literals / SGPR moves)
   using PT = gen::PatchTables<T, K>;
-  using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, T, MODE, PPW>::value>;
+  using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, T, MODE, PPW>::value, IsWide<D, K, T, MODE, PPW>::value>;
   constexpr int RS = L::RS;
   T* bufA = smem + L::offA;
   T* bufB = smem + L::offB;
-  T* bufW = smem + L::offW;
   (void)p2;
 
   const ColourBlock cb = colour_block<D, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
@@ -613,7 +640,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   // Boundary mode also replaces patch-interior nodes by 0 and does not load them: a column
   // strictly inside a patch along x0 (and x1 in 3D) needs only its two end nodes.
   if constexpr (!ADD) {
-    T* X = bufB;
+    T* X = D == 3 ? smem + L::offX : bufB;
     constexpr int NW = D == 3 ? RS * n : RS;
     const bool lo1 = s1 == 0, hi1 = s1 + n - 1 == n1d - 1;
     const bool lo2 = D == 3 && s2 == 0, hi2 = D == 3 && s2 + n - 1 == n1d - 1;
@@ -659,9 +686,12 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   if constexpr (D == 3) {
     constexpr int SJ1 = L::SJ1, SJ2 = L::SJ2, SI1 = L::SI1, SI0 = L::SI0, SA1 = L::SA1, SA2 = L::SA2;
     if constexpr (!ADD) {
-      const T* X = bufB;
-      T* PM = bufA;  // [j1][q][j2][i0]
-      T* PA = bufA + n * SJ1;
+      const T* X = smem + L::offX;
+      T* PM = smem + L::offP;  // [j1][q][j2][i0]
+      T* PA = PM + n * SJ1;
+      using T2 = typename Pair<T>::type;
+      T2* PP = reinterpret_cast<T2*>(smem + L::offP);  // paired layout: [j1][q][j2][i0]{M, A}
+      constexpr int SJP2 = L::SJP / 2;                  // pair stride
       // ---- contract x0 with Mc and Ac: lines (q, j2, j1), j1 fastest
       if constexpr (BND) {
         // Boundary form: the closure is zero on patch-interior nodes, so an x0 line with j2 and j1
@@ -756,11 +786,17 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
           const int q = task / (n * n), r = task - q * (n * n);
           const int j2 = r / n, j1 = r - j2 * n;
           if (task < NA && q < P) {
-            const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+            if constexpr (L::PR) {
+              const int o = lds_base(j1 * SJP2 + (q * n + j2) * m);
 #pragma unroll
-            for (int i = 0; i < m; ++i) {
-              PM[o + i] = om[rr][i];
-              PA[o + i] = oa[rr][i];
+              for (int i = 0; i < m; ++i) PP[o + i] = T2{om[rr][i], oa[rr][i]};
+            } else {
+              const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+#pragma unroll
+              for (int i = 0; i < m; ++i) {
+                PM[o + i] = om[rr][i];
+                PA[o + i] = oa[rr][i];
+              }
             }
           }
         }
@@ -793,8 +829,8 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
       }
       __syncthreads();
       // ---- contract x1: lines (q, j2, i0), i0 fastest; U = M1 (M0 x), V = A1 (M0 x) + M1 (A0 x)
-      T* U = bufB;  // [j2][q][i1][i0]
-      T* V = bufB + n * SJ2;
+      T* U = smem + L::offUV;  // [j2][q][i1][i0]
+      T* V = U + n * SJ2;
       if constexpr (L::AL) {
         // aliased: U/V overwrite PM/PA once every line has been read
         constexpr int NB2 = PPW * n * m, RB2 = (NB2 + NT - 1) / NT;
@@ -807,8 +843,14 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
             T pm[n], pa[n];
 #pragma unroll
             for (int j = 0; j < n; ++j) {
-              pm[j] = PM[j * SJ1 + task];
-              pa[j] = PA[j * SJ1 + task];
+              if constexpr (L::PR) {
+                const T2 v = PP[j * SJP2 + task];
+                pm[j] = v.x;
+                pa[j] = v.y;
+              } else {
+                pm[j] = PM[j * SJ1 + task];
+                pa[j] = PA[j * SJ1 + task];
+              }
             }
 #pragma unroll
             for (int i = 0; i < m; ++i) {
@@ -869,8 +911,11 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
       }
       __syncthreads();
     }
-    // ---- contract x2 (residual) and apply Sᵀ along x2: lines (q, i1, i0), i0 fastest
-    T* W4 = bufW;  // [i1][q][a2][i0]
+    // ---- contract x2 (residual) and apply Sᵀ along x2: lines (q, i1, i0), i0 fastest.  Paired
+    // layout: W4 overwrites U/V, so every line is computed before the workgroup synchronises and
+    // writes.
+    T* W4 = smem + L::offW46;  // [i1][q][a2][i0]
+    T tc[RB][m];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int task = rr * NT + tid;
@@ -882,8 +927,8 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
 #pragma unroll
           for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
         } else {
-          const T* U = bufB;
-          const T* V = bufB + n * SJ2;
+          const T* U = smem + L::offUV;
+          const T* V = U + n * SJ2;
           T u[n], v[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
@@ -901,16 +946,31 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
-        const int o = lds_base(i1 * SI1 + q * mm + i0);
-        T t[m];
-        apply_st<T, K>(res, t);
+        apply_st<T, K>(res, tc[rr]);
+        if constexpr (!L::PR) {
+          const int o = lds_base(i1 * SI1 + q * mm + i0);
 #pragma unroll
-        for (int a = 0; a < m; ++a) W4[o + a * m] = t[a];
+          for (int a = 0; a < m; ++a) W4[o + a * m] = tc[rr][a];
+        }
+      }
+    }
+    if constexpr (L::PR) {
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const int task = rr * NT + tid;
+        const int q = task / mm, r = task - q * mm;
+        const int i1 = r / m, i0 = r - i1 * m;
+        if (task < NB && q < P) {
+          const int o = lds_base(i1 * SI1 + q * mm + i0);
+#pragma unroll
+          for (int a = 0; a < m; ++a) W4[o + a * m] = tc[rr][a];
+        }
       }
     }
     __syncthreads();
     // ---- Sᵀ along x1: lines (q, a2, i0), i0 fastest
-    T* W5 = bufB;  // [i0][q][a2][a1]
+    T* W5 = smem + L::offW57;  // [i0][q][a2][a1]
     for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
       const int q = task / mm, r = task - q * mm;
@@ -928,7 +988,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
     }
     __syncthreads();
     // ---- Sᵀ along x0, scale by 1/(lam2+lam1+lam0), S along x0: lines (q, a2, a1), a1 fastest
-    T* W6 = bufW;  // [a1][q][a2][i0]
+    T* W6 = smem + L::offW46;  // [a1][q][a2][i0]
     for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
       const int q = task / mm, r = task - q * mm;
@@ -951,7 +1011,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
     }
     __syncthreads();
     // ---- S along x1: lines (q, a2, i0), i0 fastest
-    T* W7 = bufB;  // [a2][q][i1][i0]
+    T* W7 = smem + L::offW57;  // [a2][q][i1][i0]
     for (int base = 0; base < PPW * mm; base += NT) {
       const int task = base + tid;
       const int q = task / mm, r = task - q * mm;
@@ -1444,7 +1504,8 @@ struct ColourLds {
   static constexpr int value = kMfma ? MfmaLds<K, PPW>::total
                                : kMult3 ? Mult3Lds<K, PPW>::total
                                         : SmootherLds<D, K, T, MODE == kModeAdditive || MODE == kModeZero, PPW,
-                                                      LinesAlias<D, K, T, MODE, PPW>::value>::total;
+                                                      LinesAlias<D, K, T, MODE, PPW>::value,
+                                                      IsWide<D, K, T, MODE, PPW>::value>::total;
 };
 
 // One workgroup's share of a colour pass: the 3D multiplicative pass in FP64 contracts the closure
@@ -1466,7 +1527,7 @@ template <int D, int K, typename T, int MODE, int PPW>
 __global__ __launch_bounds__((ColourNT<D, K, T, MODE, PPW>::value)) void colour_pass_kernel(
     const T* __restrict__ b, T* __restrict__ x, long long n1d, int p0, int p1, int p2, int cnt0, int cnt1,
     int groups0, T res_scale, T sol_scale) {
-  __shared__ T smem[ColourLds<D, K, T, MODE, PPW>::value];
+  __shared__ __align__(16) T smem[ColourLds<D, K, T, MODE, PPW>::value];
   colour_pass_block<D, K, T, MODE, PPW>(smem, b, x, n1d, p0, p1, p2, cnt0, cnt1, groups0, res_scale, sol_scale,
                                   xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -1475,7 +1536,7 @@ __global__ __launch_bounds__((ColourNT<D, K, T, MODE, PPW>::value)) void colour_
 // levels in one launch: entry e owns blocks [begin[e], begin[e+1]).
 template <int D, int K, typename T, int MODE, int PPW>
 __global__ __launch_bounds__((ColourNT<D, K, T, MODE, PPW>::value)) void colour_pass_group_kernel(ColourPassGroup grp) {
-  __shared__ T smem[ColourLds<D, K, T, MODE, PPW>::value];
+  __shared__ __align__(16) T smem[ColourLds<D, K, T, MODE, PPW>::value];
   const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
   int e = 0;
   while (e + 1 < grp.n && (unsigned)grp.e[e + 1].block_begin <= g) ++e;
