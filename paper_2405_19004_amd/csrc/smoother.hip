@@ -533,7 +533,8 @@ constexpr int kWidePPW = 5, kWideNT = 256;
 constexpr double kWideIdle = 0.15;
 template <int D, int K, typename T, int MODE>
 struct HasWideForm {
-  static constexpr bool value = D == 3 && K == 4 && sizeof(T) == 4 && MODE == kModeMultiplicative && VPS_Q4_3D_WIDE;
+  static constexpr bool value =
+      D == 3 && K == 4 && sizeof(T) == 4 && (MODE == kModeMultiplicative || MODE == kModeZero) && VPS_Q4_3D_WIDE;
 };
 template <int D, int K, typename T, int MODE, int PPW>
 struct IsWide {
