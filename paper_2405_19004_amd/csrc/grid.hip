@@ -259,10 +259,13 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
   const bool col_out = !is_bnd(gx, n1d) && !is_bnd(gy, n1d) && gx < n1d && gy < n1d;
 
   // registers <- nb node planes zs .. zs+nb-1 of the tile (Dirichlet and outside nodes 0).
-  // Element i = rr NT + tid of a fetch is node (plane i / PL, row, column) of the tile; its byte
-  // offset from the tile corner of plane zs is the same in every fetch, so it is computed once
-  // (~0u marks a node outside the grid's interior in x0 or x1).  The planes valid in a fetch form
-  // the element range [jlo PL, jhi PL), known to the whole workgroup.
+  // Element i = rr NT + tid of a fetch is node (plane i / PL, row, column) of the tile.  Its byte
+  // offset from plane zs is the same in every fetch, so it is computed once, for the node clamped
+  // into the grid: every fetch loads every element unconditionally (no branches) and a select
+  // zeroes the elements that are not interior nodes.  Bit 31 of the offset marks a node outside
+  // the interior in x0 or x1 (offsets stay below 2^31, checked by the launcher); the planes valid
+  // in a fetch form the offset range [jlo, jhi) planes, known to the whole workgroup, which the
+  // marked offsets never fall into.
   T pre[RB];
   unsigned poff[RB];
 #pragma unroll
@@ -272,18 +275,22 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     const int r = rem / IX, c = rem - r * IX;
     const long long sy = o1 - K + r, sx = o0 - K + c;
     const bool ok = i < K * PL && sy >= 1 && sy <= n1d - 2 && sx >= 1 && sx <= n1d - 2;
-    poff[rr] = ok ? (unsigned)(((long long)j * n1d2 + (long long)r * n1d + c) * (long long)sizeof(T)) : ~0u;
+    const long long cy = sy < 0 ? 0 : sy > n1d - 1 ? n1d - 1 : sy;
+    const long long cx = sx < 0 ? 0 : sx > n1d - 1 ? n1d - 1 : sx;
+    const long long cj = j < K ? j : K - 1;
+    poff[rr] = (unsigned)((cj * n1d2 + cy * n1d + cx) * (long long)sizeof(T)) | (ok ? 0u : 0x80000000u);
   }
-  const long long corner = (o1 - K) * n1d + (o0 - K);  // negative next to the grid's low faces
+  const unsigned plane_bytes = (unsigned)(n1d2 * (long long)sizeof(T));
+  // fetches only ever cover planes 0 .. n1d-1: zs >= 0 and zs + K - 1 <= n1d - 1
   auto fetch = [&](long long zs, int nb) {
-    const int jlo = zs < 1 ? (int)(1 - zs) : 0;
-    const int jhi = (int)(zs + nb <= n1d - 1 ? nb : n1d - 1 - zs);
-    const T* plane = x + (zs * n1d2 + corner);  // only ever offset into the grid
+    const unsigned jlo = zs < 1 ? (unsigned)(1 - zs) : 0u;
+    const unsigned jhi = (unsigned)(zs + nb <= n1d - 1 ? nb : n1d - 1 - zs);
+    const unsigned lo = jlo * plane_bytes, span = jhi * plane_bytes - lo;
+    const T* plane = x + zs * n1d2;
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
-      const int i = rr * NT + tid;
-      const bool ok = poff[rr] != ~0u && i >= jlo * PL && i < jhi * PL;
-      pre[rr] = ok ? ld_lane(plane, poff[rr]) : T(0);
+      const T v = ld_lane(plane, poff[rr] & 0x7fffffffu);
+      pre[rr] = poff[rr] - lo < span ? v : T(0);
     }
   };
   auto stage = [&](int nb) {
@@ -960,10 +967,11 @@ long long op_stream_blocks(const LevelGeom& g, int* t0_out, int* cz_out) {
   return tiles * chunks;
 }
 
-// The streaming kernel addresses a cell's K node planes with 32-bit byte offsets.
+// The streaming kernel addresses a cell's K node planes with byte offsets below 2^31 (bit 31 of its
+// per-element offsets marks nodes outside the interior).
 template <int K, typename T>
 bool op_stream_fits(const LevelGeom& g) {
-  return (long long)(K + 1) * g.n1d * g.n1d * (long long)sizeof(T) < (1LL << 32);
+  return (long long)(K + 1) * g.n1d * g.n1d * (long long)sizeof(T) < (1LL << 31);
 }
 
 template <int K, typename T>

@@ -106,8 +106,11 @@ hipError_t launch_fill(int prec, void* x, long long n, double v, hipStream_t st)
 // dst = (double)src, zero = 0 (n entries each)
 hipError_t launch_widen_zero(const float* src, double* dst, double* zero, long long n, hipStream_t st);
 hipError_t launch_cast(int from_prec, const void* src, void* dst, long long n, hipStream_t st);
+// dst = interior of src, out = |dst|^2, *bad |= non-finite entries; optionally dst32 = (float)dst
+// and zero = 0 over the same range
 hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, double* dst, double* partial,
-                                     double* out, int* bad, hipStream_t st);
+                                     double* out, int* bad, hipStream_t st, float* dst32 = nullptr,
+                                     double* zero = nullptr);
 hipError_t launch_dot2(const double* a, const double* b, const double* c, const double* d, long long n,
                        double* partial, double* out, hipStream_t st);
 // x += alpha p, r -= alpha q with alpha = rz / pq, partials of r.r and r.z, and r32 = (float) r

@@ -525,9 +525,9 @@ Status pcg_begin_launch(Problem* p, int mode, const double* b, double* x, CgStat
   const long long N = p->lv[p->L].N;
   *cs = CgState();
   VPS_HIP(hipMemsetAsync(p->bad, 0, sizeof(int), p->stream));
-  VPS_HIP(launch_copy_interior_norm(p->dim, p->lv[p->L].g.n1d, b, p->r, p->partial, p->sc + kScBB, p->bad, p->stream));
-  VPS_HIP(launch_fill(0, x, N, 0.0, p->stream));
-  if (mode == 1) VPS_HIP(launch_cast(0, p->r, p->lv[p->L].b[1], N, p->stream));  // the FP32 V-cycle's input
+  // r = b (interior), x = 0 and, mixed, the FP32 copy of r (the FP32 V-cycle's input) in one pass
+  VPS_HIP(launch_copy_interior_norm(p->dim, p->lv[p->L].g.n1d, b, p->r, p->partial, p->sc + kScBB, p->bad, p->stream,
+                                    mode == 1 ? static_cast<float*>(p->lv[p->L].b[1]) : nullptr, x));
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   VPS_HIP(hipMemcpyAsync(p->host_bad, p->bad, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   return Status::ok();

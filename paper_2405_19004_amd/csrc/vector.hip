@@ -40,11 +40,13 @@ __global__ void widen_zero_kernel(const float* __restrict__ src, double* __restr
 }
 
 // dst = src with boundary entries 0 (FP64), also returns partials of src.src on the interior
-// and a non-finite flag.  I = unsigned int when every index fits in 32 bits (the coordinates then
-// take 32-bit divisions), else long long.
+// and a non-finite flag; optionally dst32 = dst rounded to FP32 and zero = 0 over the same range
+// (the CG set-up: residual, its FP32 copy and the iterate in one pass).  I = unsigned int when
+// every index fits in 32 bits (the coordinates then take 32-bit divisions), else long long.
 template <typename I>
 __global__ void copy_interior_kernel(const double* __restrict__ src, double* __restrict__ dst, int dim, long long n1d_,
-                                     long long ntot_, double* __restrict__ partial, int* __restrict__ bad) {
+                                     long long ntot_, double* __restrict__ partial, int* __restrict__ bad,
+                                     float* __restrict__ dst32, double* __restrict__ zero) {
   __shared__ double red[kRedThreads];
   double acc = 0.0;
   int nonfinite = 0;
@@ -55,6 +57,8 @@ __global__ void copy_interior_kernel(const double* __restrict__ src, double* __r
     double v = bnd ? 0.0 : src[i];
     if (!isfinite(v)) nonfinite = 1;
     dst[i] = v;
+    if (dst32) dst32[i] = (float)v;
+    if (zero) zero[i] = 0.0;
     acc = fma(v, v, acc);
   }
   red[threadIdx.x] = acc;
@@ -230,16 +234,16 @@ hipError_t launch_widen_zero(const float* src, double* dst, double* zero, long l
 }
 
 hipError_t launch_copy_interior_norm(int dim, long long n1d, const double* src, double* dst, double* partial,
-                                     double* out, int* bad, hipStream_t st) {
+                                     double* out, int* bad, hipStream_t st, float* dst32, double* zero) {
   long long ntot = dim == 2 ? n1d * n1d : n1d * n1d * n1d;
   const int parts = reduction_parts();
   // 32-bit indices need ntot plus one grid stride to stay below 2^32
   if (ntot + (long long)parts * kRedThreads < (1LL << 32))
     hipLaunchKernelGGL(copy_interior_kernel<unsigned>, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot,
-                       partial, bad);
+                       partial, bad, dst32, zero);
   else
     hipLaunchKernelGGL(copy_interior_kernel<long long>, dim3(parts), dim3(kRedThreads), 0, st, src, dst, dim, n1d, ntot,
-                       partial, bad);
+                       partial, bad, dst32, zero);
   hipLaunchKernelGGL(finalize1_kernel, dim3(1), dim3(kRedThreads), 0, st, partial, parts, out);
   return hipGetLastError();
 }
