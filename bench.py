@@ -494,7 +494,7 @@ def main():
     flops = smoother_patch_flops(D, K) * patches
     bytes_ = 4 * smoother_patch_min_words(D, K) * patches
     issued = colour_pass_issued_flops(D, K) * patches
-    lds_bytes = colour_pass_lds_bytes_3d(K, 4, 2) * patches
+    lds_bytes = colour_pass_lds_bytes_3d(K, 4, 5) * patches  # five patches per workgroup at this size
     traffic = None
     tf = os.path.join(ROOT, "profiles", "colour_pass_3d_q4_fp32_traffic.json")
     if os.path.exists(tf):
@@ -502,7 +502,7 @@ def main():
         if rec.get("source_hash") == smoother_source_hash():  # counters describe this exact kernel source
             traffic = rec.get("bytes_per_launch")
     t_hbm, t_alu = bytes_ / PEAK_HBM, flops / PEAK_FP32
-    common = {"kernel": "colour_pass_kernel<3,4,float,multiplicative,2 patches per workgroup>",
+    common = {"kernel": "colour_pass_kernel<3,4,float,multiplicative,5 patches per workgroup (wide shape)>",
               "avg_launch_us": 1e6 * t_all, "patches_per_launch": patches,
               "algorithmic_flops_per_patch": smoother_patch_flops(D, K),
               "algorithmic_words_per_patch": smoother_patch_min_words(D, K),
