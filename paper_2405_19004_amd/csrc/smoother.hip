@@ -521,9 +521,10 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   }
 }
 
-// Wide shape of the 3D Q4 FP32 multiplicative pass: five patches per workgroup on 256 threads.
-// Its 49-line stages fill 245 of 256 lanes, against 98 of 128 for the two-patch default, which
-// cuts the vector instructions per patch by about a fifth.  A row of patches along x0 that is not
+// Wide shape of the 3D Q4 FP32 colour pass (multiplicative, Boundary, and the first colour from
+// zero): five patches per workgroup on 256 threads.  Its 49-line stages fill 245 of 256 lanes,
+// against 98 of 128 for the two-patch default, which cuts the vector instructions per patch by
+// about a fifth.  A row of patches along x0 that is not
 // a multiple of five leaves a partial workgroup, so launches take it only on long rows (at most
 // kWideIdle idle patch slots per row, as a fraction of the row).
 #ifndef VPS_Q4_3D_WIDE
@@ -533,8 +534,9 @@ constexpr int kWidePPW = 5, kWideNT = 256;
 constexpr double kWideIdle = 0.15;
 template <int D, int K, typename T, int MODE>
 struct HasWideForm {
-  static constexpr bool value =
-      D == 3 && K == 4 && sizeof(T) == 4 && (MODE == kModeMultiplicative || MODE == kModeZero) && VPS_Q4_3D_WIDE;
+  static constexpr bool value = D == 3 && K == 4 && sizeof(T) == 4 &&
+                                (MODE == kModeMultiplicative || MODE == kModeZero || MODE == kModeBoundary) &&
+                                VPS_Q4_3D_WIDE;
 };
 template <int D, int K, typename T, int MODE, int PPW>
 struct IsWide {
@@ -701,12 +703,10 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
         constexpr int NF = 4 * (n - 1);
         // face tasks padded to whole waves, so that no wave mixes the two kinds of line
         constexpr int FP = (PPW * NF + 63) / 64 * 64, NTASK = FP + PPW * mm;
-        for (int base = 0; base < NTASK; base += NT) {
-          const int task = base + tid;
-          if (task >= NTASK || (task >= PPW * NF && task < FP)) continue;
-          int q, j2, j1;
-          const bool face = task < FP;
-          if (face) {
+        // task -> line (q, j2, j1); false for padding and for patches past the workgroup's last
+        auto line_of = [&](int task, int& q, int& j2, int& j1) -> bool {
+          if (task >= NTASK || (task >= PPW * NF && task < FP)) return false;
+          if (task < FP) {
             q = task / NF;
             const int f = task - q * NF;
             if (f < n) {
@@ -726,30 +726,77 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
             j2 = 1 + c / m;
             j1 = 1 + (c - (c / m) * m);
           }
-          if (q >= P) continue;
-          const int row = lds_base((j2 * n + j1) * RS + 2 * K * q);
-          const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+          return q < P;
+        };
+        // M and A rows of one line into sm, sa
+        auto contract = [&](bool face, int row, T* sm, T* sa) {
           if (face) {
             T in[n];
 #pragma unroll
             for (int j = 0; j < n; ++j) in[j] = X[row + j];
 #pragma unroll
             for (int i = 0; i < m; ++i) {
-              T sm = T(0), sa = T(0);
+              T am = T(0), aa = T(0);
 #pragma unroll
               for (int j = 0; j < n; ++j) {
-                sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
-                sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
+                am = fma_tab(PT::Mc[i * n + j], in[j], am);
+                aa = fma_tab(PT::Ac[i * n + j], in[j], aa);
               }
-              PM[o + i] = sm;
-              PA[o + i] = sa;
+              sm[i] = am;
+              sa[i] = aa;
             }
           } else {
             const T e0 = X[row], e1 = X[row + n - 1];
 #pragma unroll
             for (int i = 0; i < m; ++i) {
-              PM[o + i] = fma_tab(PT::Mc[i * n], e0, fma_tab(PT::Mc[i * n + n - 1], e1, T(0)));
-              PA[o + i] = fma_tab(PT::Ac[i * n], e0, fma_tab(PT::Ac[i * n + n - 1], e1, T(0)));
+              sm[i] = fma_tab(PT::Mc[i * n], e0, fma_tab(PT::Mc[i * n + n - 1], e1, T(0)));
+              sa[i] = fma_tab(PT::Ac[i * n], e0, fma_tab(PT::Ac[i * n + n - 1], e1, T(0)));
+            }
+          }
+        };
+        if constexpr (L::AL) {
+          // aliased: every line is read and contracted, then PM/PA overwrite X
+          constexpr int RA = (NTASK + NT - 1) / NT;
+          T om[RA][m], oa[RA][m];
+#pragma unroll
+          for (int rr = 0; rr < RA; ++rr) {
+            const int task = rr * NT + tid;
+            int q, j2, j1;
+            if (line_of(task, q, j2, j1))
+              contract(task < FP, lds_base((j2 * n + j1) * RS + 2 * K * q), om[rr], oa[rr]);
+          }
+          __syncthreads();
+#pragma unroll
+          for (int rr = 0; rr < RA; ++rr) {
+            const int task = rr * NT + tid;
+            int q, j2, j1;
+            if (line_of(task, q, j2, j1)) {
+              if constexpr (L::PR) {
+                const int o = lds_base(j1 * SJP2 + (q * n + j2) * m);
+#pragma unroll
+                for (int i = 0; i < m; ++i) PP[o + i] = T2{om[rr][i], oa[rr][i]};
+              } else {
+                const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+#pragma unroll
+                for (int i = 0; i < m; ++i) {
+                  PM[o + i] = om[rr][i];
+                  PA[o + i] = oa[rr][i];
+                }
+              }
+            }
+          }
+        } else {
+          for (int base = 0; base < NTASK; base += NT) {
+            const int task = base + tid;
+            int q, j2, j1;
+            if (!line_of(task, q, j2, j1)) continue;
+            const int o = lds_base(j1 * SJ1 + (q * n + j2) * m);
+            T sm[m], sa[m];
+            contract(task < FP, lds_base((j2 * n + j1) * RS + 2 * K * q), sm, sa);
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              PM[o + i] = sm[i];
+              PA[o + i] = sa[i];
             }
           }
         }
