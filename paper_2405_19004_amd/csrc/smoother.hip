@@ -626,14 +626,42 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
 
   if constexpr (ZERO) {
     // 0 on every closure node of the workgroup that is not a patch interior (neighbouring
-    // workgroups write the same zeros on shared faces; no interior of the colour lies there)
-    constexpr int NZ = D == 3 ? n * n * RS : n * RS;
+    // workgroups write the same zeros on shared faces; no interior of the colour lies there).
+    // Those nodes are the closure rows on its faces, whole, and on the other rows the columns
+    // between patches (every 2k-th); rows run along x0.
+    constexpr int NFR = D == 3 ? 4 * (n - 1) : 2;  // face rows (j2, j1) / (j1)
+    constexpr int NIR = D == 3 ? m * m : m;        // other rows
+    constexpr int NZF = NFR * RS, NZ = NZF + NIR * (PPW + 1);
     for (int w = tid; w < NZ; w += NT) {
-      const int c = w % RS, r = w / RS;  // r = j2 * n + j1 (3D) or j1 (2D)
-      const int j1 = D == 3 ? r % n : r, j2 = D == 3 ? r / n : 0;
-      const bool inner = c % (2 * K) != 0 && j1 > 0 && j1 < n - 1 && (D == 2 || (j2 > 0 && j2 < n - 1));
-      if (c < seg && !inner)
-        st_lane(xo, (unsigned)((D == 3 ? j2 * ld2 : 0) + j1 * ld1 + c) * (unsigned)sizeof(T), T(0));
+      int j1, j2 = 0, c;
+      if (w < NZF) {
+        const int f = w / RS;
+        c = w - f * RS;
+        if constexpr (D == 3) {
+          if (f < n) {
+            j2 = 0;
+            j1 = f;
+          } else if (f < 2 * n) {
+            j2 = n - 1;
+            j1 = f - n;
+          } else {
+            j2 = 1 + (f - 2 * n) / 2;
+            j1 = (f & 1) ? n - 1 : 0;  // f - 2n and f have the same parity (2n even)
+          }
+        } else {
+          j1 = f == 0 ? 0 : n - 1;
+        }
+      } else {
+        const int v = w - NZF, r = v / (PPW + 1);
+        c = 2 * K * (v - r * (PPW + 1));
+        if constexpr (D == 3) {
+          j2 = 1 + r / m;
+          j1 = 1 + (r - (r / m) * m);
+        } else {
+          j1 = 1 + r;
+        }
+      }
+      if (c < seg) st_lane(xo, (unsigned)((D == 3 ? j2 * ld2 : 0) + j1 * ld1 + c) * (unsigned)sizeof(T), T(0));
     }
   }
 
