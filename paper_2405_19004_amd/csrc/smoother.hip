@@ -228,6 +228,13 @@ __device__ __forceinline__ void apply_s(const T (&t)[2 * K - 1], T (&w)[2 * K - 
   }
 }
 
+// Degrees (bit K) whose FP64 3D multiplicative pass takes the aliased LDS layout below: measured
+// 11-45% faster for degrees 2-7 (occupancy: 3D Q4 goes from 33 to 17 KB of LDS, from 8 to 18 waves
+// per compute unit), equal at degree 1.
+#ifndef VPS_MULT3_ALIAS_MASK
+#define VPS_MULT3_ALIAS_MASK 0xFC
+#endif
+
 // LDS of the 3D multiplicative pass below (T words).  Buffer A holds PM, PA [i2][j1][c], later the
 // results of stages C and E; buffer B holds U, V, later those of D and F.  Every transpose buffer
 // after PM/PA is laid out [loop index of the reading stage][reading task], the outer stride padded
@@ -249,7 +256,15 @@ struct Mult3Lds {
   static constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
   static constexpr int A = max3(2 * PM, m * SW, m * SW3);
   static constexpr int B = max3(2 * n * SU, m * SW2, m * SW4);
-  static constexpr int total = A + B;
+  // Aliased layout: PM/PA, U/V and the C->D buffer all start at word 0 (stages B and C compute
+  // every line, the workgroup synchronises, then they write over their inputs); the D->E and F->G
+  // buffers follow the larger of C->D and E->F, which starts at 0 again.
+  static constexpr bool AL = ((VPS_MULT3_ALIAS_MASK) >> K) & 1;
+  static constexpr int X1 = m * SW > m * SW3 ? m * SW : m * SW3;
+  static constexpr int ALT = max3(2 * PM, 2 * n * SU, X1 + (m * SW2 > m * SW4 ? m * SW2 : m * SW4));
+  static constexpr int total = AL ? ALT : A + B;
+  static constexpr int offP = 0, offUV = AL ? 0 : A;
+  static constexpr int offW = 0, offW2 = AL ? X1 : A, offW3 = 0, offW4 = AL ? X1 : A;
 };
 
 // 3D multiplicative colour pass, closure contracted along x2 first.  Every thread of stage A loads
@@ -275,8 +290,6 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   using PT = gen::PatchTables<T, K>;
   using L = Mult3Lds<K, PPW>;
   constexpr int RS = L::RS;
-  T* bufA = smem;
-  T* bufB = smem + L::A;
 
   const ColourBlock cb = colour_block<3, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
   const int P = cb.count;
@@ -314,8 +327,8 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   //      boundary) follow.  Dirichlet nodes count as 0 (the boundary entries of x are not read as
   //      values).
   {
-    T* PM = bufA;
-    T* PA = bufA + L::PM;
+    T* PM = smem + L::offP;
+    T* PA = PM + L::PM;
     constexpr int NF = 2 * RS + (n - 2) * (PPW + 1);  // face columns
     constexpr int NA = NB + NF;
     const bool lo0 = s0 == 0, hi0 = s0 + seg - 1 == n1d - 1;
@@ -374,48 +387,75 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
   __syncthreads();
   // ---- B: x0 lines (q, i2, j1), j1 fastest -> U, V
   {
-    const T* PM = bufA;
-    const T* PA = bufA + L::PM;
-    T* U = bufB;
-    T* V = bufB + n * L::SU;
-    for (int base = 0; base < PPW * m * n; base += NT) {
-      const int task = base + tid;
+    const T* PM = smem + L::offP;
+    const T* PA = PM + L::PM;
+    T* U = smem + L::offUV;
+    T* V = U + n * L::SU;
+    // x0 line of a task: U and V rows into su, sv; false past the workgroup's patches
+    auto line = [&](int task, T* su, T* sv) -> bool {
       const int q = task / (m * n), r = task - q * (m * n);
       const int i2 = r / n, j1 = r - i2 * n;
-      if (task < PPW * m * n && q < P) {
-        const int ri = lds_base((i2 * n + j1) * RS + 2 * K * q);
-        T pm[n], pa[n];
+      if (task >= PPW * m * n || q >= P) return false;
+      const int ri = lds_base((i2 * n + j1) * RS + 2 * K * q);
+      T pm[n], pa[n];
+#pragma unroll
+      for (int c = 0; c < n; ++c) {
+        pm[c] = PM[ri + c];
+        pa[c] = PA[ri + c];
+      }
+#pragma unroll
+      for (int i = 0; i < m; ++i) {
+        T au = T(0), av = T(0);
 #pragma unroll
         for (int c = 0; c < n; ++c) {
-          pm[c] = PM[ri + c];
-          pa[c] = PA[ri + c];
+          au = fma_tab(PT::Mc[i * n + c], pm[c], au);
+          av = fma_tab(PT::Ac[i * n + c], pm[c], av);
+          av = fma_tab(PT::Mc[i * n + c], pa[c], av);
         }
-        const int o = lds_base(j1 * L::SU + (q * m + i2) * m);
+        su[i] = au;
+        sv[i] = av;
+      }
+      return true;
+    };
+    auto put = [&](int task, const T* su, const T* sv) {
+      const int q = task / (m * n), r = task - q * (m * n);
+      const int i2 = r / n, j1 = r - i2 * n;
+      const int o = lds_base(j1 * L::SU + (q * m + i2) * m);
 #pragma unroll
-        for (int i = 0; i < m; ++i) {
-          T su = T(0), sv = T(0);
+      for (int i = 0; i < m; ++i) {
+        U[o + i] = su[i];
+        V[o + i] = sv[i];
+      }
+    };
+    if constexpr (L::AL) {
+      // U/V overwrite PM/PA: every line first, then the writes
+      constexpr int RB2 = (PPW * m * n + NT - 1) / NT;
+      T su[RB2][m], sv[RB2][m];
+      bool ok[RB2];
 #pragma unroll
-          for (int c = 0; c < n; ++c) {
-            su = fma_tab(PT::Mc[i * n + c], pm[c], su);
-            sv = fma_tab(PT::Ac[i * n + c], pm[c], sv);
-            sv = fma_tab(PT::Mc[i * n + c], pa[c], sv);
-          }
-          U[o + i] = su;
-          V[o + i] = sv;
-        }
+      for (int rr = 0; rr < RB2; ++rr) ok[rr] = line(rr * NT + tid, su[rr], sv[rr]);
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < RB2; ++rr)
+        if (ok[rr]) put(rr * NT + tid, su[rr], sv[rr]);
+    } else {
+      for (int base = 0; base < PPW * m * n; base += NT) {
+        T su[m], sv[m];
+        if (line(base + tid, su, sv)) put(base + tid, su, sv);
       }
     }
   }
   __syncthreads();
-  // ---- C: x1 lines (q, i2, i0): residual, then S^T along x1
+  // ---- C: x1 lines (q, i2, i0): residual, then S^T along x1.  Aliased layout: the C->D buffer
+  //      overwrites U/V, so every line is computed before the workgroup synchronises and writes.
+  T tc[RB][m];
 #pragma unroll
   for (int rr = 0; rr < RB; ++rr) {
     const int task = rr * NT + tid;
     const int q = task / mm;
     if (task < NB && q < P) {
-      const T* U = bufB;
-      const T* V = bufB + n * L::SU;
-      T* W = bufA;
+      const T* U = smem + L::offUV;
+      const T* V = U + n * L::SU;
       T u[n], v[n];
 #pragma unroll
       for (int j = 0; j < n; ++j) {
@@ -433,12 +473,22 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
         }
         res[i] = fma(-res_scale, sres, bpre[rr][i]);
       }
-      T t[m];
-      apply_st<T, K>(res, t);
-      const int r = task - q * mm, i2 = r / m, i0 = r - i2 * m;
-      const int o = lds_base(i2 * L::SW + q * mm + i0);
+      apply_st<T, K>(res, tc[rr]);
+    }
+  }
+  if constexpr (L::AL) __syncthreads();
+  {
+    T* W = smem + L::offW;
 #pragma unroll
-      for (int a = 0; a < m; ++a) W[o + a * m] = t[a];
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / mm;
+      if (task < NB && q < P) {
+        const int r = task - q * mm, i2 = r / m, i0 = r - i2 * m;
+        const int o = lds_base(i2 * L::SW + q * mm + i0);
+#pragma unroll
+        for (int a = 0; a < m; ++a) W[o + a * m] = tc[rr][a];
+      }
     }
   }
   __syncthreads();
@@ -447,8 +497,8 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
     const int task = base + tid;
     const int q = task / mm;
     if (task < PPW * mm && q < P) {
-      const T* W = bufA;
-      T* W2 = bufB;
+      const T* W = smem + L::offW;
+      T* W2 = smem + L::offW2;
       const int r = task - q * mm, a1 = r / m, i0 = r - a1 * m;
       T in[m];
 #pragma unroll
@@ -466,8 +516,8 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
     const int task = base + tid;
     const int q = task / mm;
     if (task < PPW * mm && q < P) {
-      const T* W2 = bufB;
-      T* W3 = bufA;
+      const T* W2 = smem + L::offW2;
+      T* W3 = smem + L::offW3;
       const DevTables<T>& tb = tab_fresh<T>(K);
       const int r = task - q * mm, a2 = r / m, a1 = r - a2 * m;
       T in[m], z[m];
@@ -489,8 +539,8 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
     const int task = base + tid;
     const int q = task / mm;
     if (task < PPW * mm && q < P) {
-      const T* W3 = bufA;
-      T* W4 = bufB;
+      const T* W3 = smem + L::offW3;
+      T* W4 = smem + L::offW4;
       const int r = task - q * mm, a2 = r / m, i0 = r - a2 * m;
       T in[m];
 #pragma unroll
@@ -509,7 +559,7 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
     const int task = rr * NT + tid;
     const int q = task / mm;
     if (task < NB && q < P) {
-      const T* W4 = bufB;
+      const T* W4 = smem + L::offW4;
       T in[m];
 #pragma unroll
       for (int a = 0; a < m; ++a) in[a] = W4[a * L::SW4 + task];
@@ -524,9 +574,9 @@ __device__ __forceinline__ void colour_pass_mult3(T* __restrict__ smem, const T*
 // Wide shape of the 3D Q4 FP32 colour pass (multiplicative, Boundary, and the first colour from
 // zero): five patches per workgroup on 256 threads.  Its 49-line stages fill 245 of 256 lanes,
 // against 98 of 128 for the two-patch default, which cuts the vector instructions per patch by
-// about a fifth.  A row of patches along x0 that is not
-// a multiple of five leaves a partial workgroup, so launches take it only on long rows (at most
-// kWideIdle idle patch slots per row, as a fraction of the row).
+// about a fifth.  A row of patches along x0 that is not a multiple of five leaves a partial
+// workgroup, so launches take it only on long rows (at most kWideIdle idle patch slots per row, as a
+// fraction of the row).
 #ifndef VPS_Q4_3D_WIDE
 #define VPS_Q4_3D_WIDE 1
 #endif
