@@ -146,10 +146,14 @@ struct SmootherLds {
   static constexpr int PR3a = X3 > PP3 ? X3 : PP3;
   static constexpr int PR3b = UV3 > W46 + W57 ? UV3 : W46 + W57;
   static constexpr int PR3 = PR3a > PR3b ? PR3a : PR3b;
-  static constexpr int total = D == 3 ? (PR ? PR3 : AL ? AL3 : A3 + B3) : A2 + B2;
-  // 2D: PM/PA and the diagonalisation buffers at offA, the closure and W at offB
-  static constexpr int offA = 0;
-  static constexpr int offB = D == 3 ? (AL ? 0 : A3) : A2;
+  // ---- aliased 2D layout (multiplicative): X, PM/PA and the x1 stage's output W start at word 0
+  // (the x0 and x1 stages compute every line, the workgroup synchronises, then they write over
+  // their inputs); W2 follows W
+  static constexpr bool AL2 = ALIASv && D == 2 && !ADD;
+  static constexpr int AL2a = X2 > P2 ? X2 : P2;
+  static constexpr int AL2T = AL2a > m * T0 + m * TA ? AL2a : m * T0 + m * TA;
+  static constexpr int total = D == 3 ? (PR ? PR3 : AL ? AL3 : A3 + B3) : (AL2 ? AL2T : A2 + B2);
+  static constexpr int offX2 = AL2 ? 0 : A2, offP2 = 0, offW = AL2 ? 0 : A2, offW2 = AL2 ? m * T0 : 0;
   // 3D buffers
   static constexpr int offX = AL ? 0 : A3;
   static constexpr int offP = 0;
@@ -593,12 +597,19 @@ struct IsWide {
   static constexpr bool value = HasWideForm<D, K, T, MODE>::value && PPW == kWidePPW;
 };
 
-// The aliased LDS layout serves the default shape of the 3D multiplicative pass where the shape
-// asks for it, and the wide shape.
+// Degrees (bit K) whose default 2D multiplicative shape takes the aliased LDS layout.
+#ifndef VPS_2D_ALIAS_MASK
+#define VPS_2D_ALIAS_MASK 0xFE
+#endif
+
+// The aliased LDS layout serves the default shape of the multiplicative pass where the shape asks
+// for it, and the wide shape.
 template <int D, int K, typename T, int MODE, int PPW>
 struct LinesAlias {
   static constexpr bool value =
       (D == 3 && MODE == kModeMultiplicative && SmootherShape<3, K>::ALIAS && PPW == SmootherShape<3, K>::PPW) ||
+      (D == 2 && MODE == kModeMultiplicative && (((VPS_2D_ALIAS_MASK) >> K) & 1) &&
+       PPW == SmootherShape<2, K>::PPW) ||
       IsWide<D, K, T, MODE, PPW>::value;
 };
 
@@ -617,8 +628,6 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   using PT = gen::PatchTables<T, K>;
   using L = SmootherLds<D, K, T, ADD, PPW, LinesAlias<D, K, T, MODE, PPW>::value, IsWide<D, K, T, MODE, PPW>::value>;
   constexpr int RS = L::RS;
-  T* bufA = smem + L::offA;
-  T* bufB = smem + L::offB;
   (void)p2;
 
   const ColourBlock cb = colour_block<D, K, PPW>(blk, p0, p1, p2, cnt0, cnt1, groups0);
@@ -721,7 +730,7 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
   // Boundary mode also replaces patch-interior nodes by 0 and does not load them: a column
   // strictly inside a patch along x0 (and x1 in 3D) needs only its two end nodes.
   if constexpr (!ADD) {
-    T* X = D == 3 ? smem + L::offX : bufB;
+    T* X = smem + (D == 3 ? L::offX : L::offX2);
     constexpr int NW = D == 3 ? RS * n : RS;
     const bool lo1 = s1 == 0, hi1 = s1 + n - 1 == n1d - 1;
     const bool lo2 = D == 3 && s2 == 0, hi2 = D == 3 && s2 + n - 1 == n1d - 1;
@@ -1174,10 +1183,50 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
     // ================================ 2D =====================================
     constexpr int T1 = L::T1, T0 = L::T0, TA = L::TA;
     if constexpr (!ADD) {
-      const T* X = bufB;
-      T* PM = bufA;  // [j1][q][i0]
-      T* PA = bufA + n * T1;
+      const T* X = smem + L::offX2;
+      T* PM = smem + L::offP2;  // [j1][q][i0]
+      T* PA = PM + n * T1;
       // ---- contract x0 with Mc and Ac: lines (q, j1), q fastest
+      if constexpr (L::AL2) {
+        // aliased: every line is read and contracted, then PM/PA overwrite X
+        constexpr int R0 = (PPW * n + NT - 1) / NT;
+        T om[R0][m], oa[R0][m];
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr) {
+          const int task = rr * NT + tid;
+          const int j1 = task / PPW, q = task - j1 * PPW;
+          if (task < PPW * n && q < P) {
+            T in[n];
+#pragma unroll
+            for (int j = 0; j < n; ++j) in[j] = X[j1 * RS + 2 * K * q + j];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              T sm = T(0), sa = T(0);
+#pragma unroll
+              for (int j = 0; j < n; ++j) {
+                sm = fma_tab(PT::Mc[i * n + j], in[j], sm);
+                sa = fma_tab(PT::Ac[i * n + j], in[j], sa);
+              }
+              om[rr][i] = sm;
+              oa[rr][i] = sa;
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < R0; ++rr) {
+          const int task = rr * NT + tid;
+          const int j1 = task / PPW, q = task - j1 * PPW;
+          if (task < PPW * n && q < P) {
+            const int o = lds_base(j1 * T1 + q * m);
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+              PM[o + i] = om[rr][i];
+              PA[o + i] = oa[rr][i];
+            }
+          }
+        }
+      } else
       for (int base = 0; base < PPW * n; base += NT) {
         const int task = base + tid;
         const int j1 = task / PPW, q = task - j1 * PPW;
@@ -1205,20 +1254,22 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
       __syncthreads();
     }
     // ---- residual along x1, r = b - (A1 (M0 x) + M1 (A0 x)) (or r = b), then Sᵀ along x1:
-    //      lines (q, i0), i0 fastest
-    T* W = bufB;  // [i0][q][a1]
+    //      lines (q, i0), i0 fastest.  Aliased layout: W overwrites PM/PA, so every line is
+    //      computed before the workgroup synchronises and writes.
+    T* W = smem + L::offW;  // [i0][q][a1]
+    T tw[RB][m];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) {
       const int task = rr * NT + tid;
-      const int q = task / m, i0 = task - q * m;
+      const int q = task / m;
       if (task < NB && q < P) {
         T res[m];
         if constexpr (ADD) {
 #pragma unroll
           for (int i = 0; i < m; ++i) res[i] = bpre[rr][i];
         } else {
-          const T* PM = bufA;
-          const T* PA = bufA + n * T1;
+          const T* PM = smem + L::offP2;
+          const T* PA = PM + n * T1;
           T pm[n], pa[n];
 #pragma unroll
           for (int j = 0; j < n; ++j) {
@@ -1236,16 +1287,23 @@ __device__ __forceinline__ void colour_pass_lines(T* __restrict__ smem, const T*
             res[i] = fma(-res_scale, s, bpre[rr][i]);
           }
         }
-        const int o = lds_base(i0 * T0 + q * m);
-        T t[m];
-        apply_st<T, K>(res, t);
+        apply_st<T, K>(res, tw[rr]);
+      }
+    }
+    if constexpr (L::AL2) __syncthreads();
 #pragma unroll
-        for (int a = 0; a < m; ++a) W[o + a] = t[a];
+    for (int rr = 0; rr < RB; ++rr) {
+      const int task = rr * NT + tid;
+      const int q = task / m, i0 = task - q * m;
+      if (task < NB && q < P) {
+        const int o = lds_base(i0 * T0 + q * m);
+#pragma unroll
+        for (int a = 0; a < m; ++a) W[o + a] = tw[rr][a];
       }
     }
     __syncthreads();
     // ---- Sᵀ along x0, scale by 1/(lam1+lam0), S along x0: lines (q, a1), a1 fastest
-    T* W2 = bufA;  // [a1][q][i0]
+    T* W2 = smem + L::offW2;  // [a1][q][i0]
     for (int base = 0; base < PPW * m; base += NT) {
       const int task = base + tid;
       const int q = task / m, a1 = task - q * m;
