@@ -114,6 +114,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the closed-loop mixed serving run of --serve requests (for profiling)")
+    ap.add_argument("--serve-slots", type=int, default=16, help="requests the server keeps active at once")
+    ap.add_argument("--serve-replays", action="store_true",
+                    help="with --serve-only: every replay (Poisson, FP64, one at a time), not only the closed loop")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only 8 FP32 and 8 FP64 colour passes on the finest level, twice (for counter runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -404,7 +407,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 4}))
         return
     if a.serve_only:
-        print(json.dumps(serving_run(v, a.serve, closed_loop_only=True)))
+        print(json.dumps(serving_run(v, a.serve, max_active=a.serve_slots, closed_loop_only=not a.serve_replays)))
         return
     FL = v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY
     P = v.Problem(D, K, L, FL | v.VPS_FLAG_POST_SAME_ORDER)
@@ -538,7 +541,7 @@ def main():
     progress("headline solve, components and colour-pass roofline done")
 
     if a.serve > 0:
-        out["serving"] = serving_run(v, a.serve)
+        out["serving"] = serving_run(v, a.serve, max_active=a.serve_slots)
         progress("serving run done (%d requests)" % a.serve)
     if not a.no_table7:
         out["table7"] = table7_run(v, torch)
