@@ -224,8 +224,9 @@ struct OpStream {
   static constexpr int IX = TX + K + 1, IY = TY + K + 1;  // input extents [o - K, o + T]
 };
 
-// pq_part != null (y = A x only): pq_part[block] = sum over the block's outputs of x_i y_i in FP64,
-// the partial sums of the CG product p.Ap.
+// pq_part != null: pq_part[block] = the block's partial sum in FP64 of x_i y_i (y = A x: the CG
+// product p.Ap) or, for the residual, of r_i^2 with r = b - A x, which is then not stored (y may be
+// null): the norm of the true residual.
 template <int K, typename T, bool RESID>
 __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* __restrict__ x, const T* __restrict__ b,
                                                                      T* __restrict__ y, long long n1d, int tiles0,
@@ -414,8 +415,12 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
       if (col_out && zg >= 1) {
         const long long gi = zg * n1d2 + gy * n1d + gx;
         const T v = RESID ? b[gi] - scale * s : scale * s;
-        y[gi] = v;
-        if (!RESID && pq_part) pq = fma((double)x[gi], (double)v, pq);
+        if (RESID && sizeof(T) == 8 && pq_part) {
+          pq = fma((double)v, (double)v, pq);
+        } else {
+          y[gi] = v;
+          if (!RESID && pq_part) pq = fma((double)x[gi], (double)v, pq);
+        }
       }
     }
     carry = T(0);
@@ -424,7 +429,8 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
     zm[0] = zm[K];
     zq[0] = zq[K];
   }
-  if (!RESID && pq_part) {
+  // (the FP32 residual never takes partial sums: no reduction buffer for it)
+  if (pq_part && (!RESID || sizeof(T) == 8)) {
     // fixed-order block reduction (the LDS buffers are free after the last barrier of the loop)
     __shared__ double red[NT];
     red[tid] = pq;
@@ -985,7 +991,7 @@ hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, vo
   const T scale = (T)g.h;  // A_h = h A_1 in 3D
   if (b)
     hipLaunchKernelGGL((op_stream_kernel<K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
-                       (const T*)b, (T*)y, g.n1d, t0, t0, cz, scale, (double*)nullptr);
+                       (const T*)b, (T*)y, g.n1d, t0, t0, cz, scale, pq_part);
   else
     hipLaunchKernelGGL((op_stream_kernel<K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
                        (const T*)nullptr, (T*)y, g.n1d, t0, t0, cz, scale, pq_part);
@@ -1225,7 +1231,36 @@ hipError_t op_pq_k(const LevelGeom& g, const double* p, double* q, double* part,
   *fused = true;
   return hipGetLastError();
 }
+
+template <int K>
+hipError_t res_norm_k(const LevelGeom& g, const double* x, const double* b, double* part, int max_parts,
+                      double* out, hipStream_t st, bool* fused) {
+  int t0, cz;
+  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
+  if (blocks > max_parts || !op_stream_fits<K, double>(g)) return hipSuccess;
+  hipError_t e = op_stream_launch<K, double>(g, x, b, nullptr, st, part);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)part, (int)blocks, out);
+  *fused = true;
+  return hipGetLastError();
+}
 }  // namespace
+
+hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part, int max_parts,
+                                 double* out, hipStream_t st, bool* fused) {
+  *fused = false;
+  if (!(g.dim == 3 && g.ncells >= kOpStreamMinCells)) return hipSuccess;
+  switch (g.k) {
+    case 1: return res_norm_k<1>(g, x, b, part, max_parts, out, st, fused);
+    case 2: return res_norm_k<2>(g, x, b, part, max_parts, out, st, fused);
+    case 3: return res_norm_k<3>(g, x, b, part, max_parts, out, st, fused);
+    case 4: return res_norm_k<4>(g, x, b, part, max_parts, out, st, fused);
+    case 5: return res_norm_k<5>(g, x, b, part, max_parts, out, st, fused);
+    case 6: return res_norm_k<6>(g, x, b, part, max_parts, out, st, fused);
+    case 7: return res_norm_k<7>(g, x, b, part, max_parts, out, st, fused);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
                               hipStream_t st, bool* fused) {

@@ -623,8 +623,14 @@ Status pcg_end_launch(Problem* p, const double* b, const double* x, const CgStat
   *pending = false;
   if (cs->stats.status == -6 || cs->bb == 0.0) return Status::ok();
   const long long N = p->lv[p->L].N;
-  VPS_HIP(launch_operator(p->geom(p->L), 0, x, b, p->q, p->stream));  // q = b - A x (interior)
-  VPS_HIP(launch_dot2(p->q, p->q, nullptr, nullptr, N, p->partial, p->sc + kScTrue, p->stream));
+  // |b - A x|^2 in one pass where the streaming operator serves the level, else through q
+  bool fused = false;
+  VPS_HIP(launch_residual_norm2(p->geom(p->L), x, b, p->partial, 2 * reduction_parts(), p->sc + kScTrue, p->stream,
+                                &fused));
+  if (!fused) {
+    VPS_HIP(launch_operator(p->geom(p->L), 0, x, b, p->q, p->stream));  // q = b - A x (interior)
+    VPS_HIP(launch_dot2(p->q, p->q, nullptr, nullptr, N, p->partial, p->sc + kScTrue, p->stream));
+  }
   VPS_HIP(hipMemcpyAsync(p->host_sc, p->sc, kScCount * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   *pending = true;
   return Status::ok();
