@@ -507,6 +507,12 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
 #pragma unroll
       for (int j = 0; j < TI; ++j) in[j] = T1[j * TO + xo];
       const long long gx = f0 + xo;
+      T old[TO];  // own outputs: all loads before the first store
+#pragma unroll
+      for (int yo = 0; yo < TO; ++yo) {
+        const long long gy = f1 + yo;
+        old[yo] = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df) ? xf[gy * n1df + gx] : T(0);
+      }
 #pragma unroll
       for (int yo = 0; yo < TO; ++yo) {
         const int cc = yo / (2 * K), q = yo % (2 * K);
@@ -517,7 +523,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
           s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gy = f1 + yo;
-        if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] += s;
+        if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] = old[yo] + s;
       }
     }
   } else {
@@ -549,6 +555,14 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
       for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
       const long long gx = f0 + xo, gy = f1 + yo;
       const bool ok = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df);
+      // the thread's outputs are its own (tiles do not overlap): every old value is loaded before
+      // the first store, so the loads are in flight together instead of one after each store
+      T old[TO];
+#pragma unroll
+      for (int zo = 0; zo < TO; ++zo) {
+        const long long gz = f2 + zo;
+        old[zo] = ok && gz < n1df && !is_bnd(gz, n1df) ? xf[gz * nf2 + gy * n1df + gx] : T(0);
+      }
 #pragma unroll
       for (int zo = 0; zo < TO; ++zo) {
         const int cc = zo / (2 * K), q = zo % (2 * K);
@@ -559,7 +573,7 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
           s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
         const long long gz = f2 + zo;
-        if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] += s;
+        if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] = old[zo] + s;
       }
     }
   }
