@@ -579,98 +579,6 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   }
 }
 
-// -------------------------------------------------- separable restriction
-
-// One axis of r_coarse = (P1 x P1 x P1)^T r_fine.  `out` has extents (o2, o1, o0); `in` has the
-// same extents except along AXIS, where it has the fine length nf (out has the coarse length nc).
-// Coarse node J = k*C + a collects fine nodes 2k(C-1) + t with weights Rb[a][t] (t in [0, 4k] for
-// a vertex, [2k, 4k] otherwise).  Fine boundary nodes along AXIS are read as 0 and coarse
-// boundary nodes along AXIS are written 0; in the first pass (`mask_other`) outputs on the
-// Dirichlet boundary of the other, still fine, axes are written 0 too.  One thread per output,
-// lanes along x0, the other two coordinates from the grid (no index division): coalesced.
-template <int K, typename T, int AXIS>
-__global__ void restrict_pass_kernel(const T* __restrict__ in, T* __restrict__ out, int nf, int nc, int o0, int o1,
-                                     int o2) {
-  constexpr int RW = 4 * K + 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // (i1, i0) of one output plane
-  if (t >= o0 * o1) return;
-  const int i1 = t / o0, i0 = t - i1 * o0;
-  const long long ie0 = AXIS == 0 ? nf : o0, ie1 = AXIS == 1 ? nf : o1;
-  const long long stride = AXIS == 0 ? 1 : AXIS == 1 ? ie0 : ie0 * ie1;
-  using CT = gen::CellTables<T, K>;
-  for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
-    const long long oidx = ((long long)i2 * o1 + i1) * o0 + i0;
-    const int J = AXIS == 0 ? i0 : AXIS == 1 ? i1 : i2;
-    if (J == 0 || J == nc - 1) {
-      out[oidx] = T(0);
-      continue;
-    }
-    const long long base = AXIS == 0 ? ((long long)i2 * ie1 + i1) * ie0
-                         : AXIS == 1 ? (long long)i2 * ie1 * ie0 + i0
-                                     : (long long)i1 * ie0 + i0;
-    const T* p = in + base;
-    const int a = J % K;
-    const int f0 = 2 * (J - a) - 2 * K;  // fine index of band position 0
-    T s = T(0);
-    if (a == 0) {
-#pragma unroll
-      for (int tt = 0; tt < RW; ++tt) {
-        const int f = f0 + tt;
-        const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
-        const T v = p[fc * stride];
-        s = fma_tab(CT::Rb[tt], (f > 0 && f < nf - 1) ? v : T(0), s);
-      }
-    } else {
-#pragma unroll
-      for (int tt = 2 * K; tt < RW; ++tt) {
-        const int f = f0 + tt;  // in [1, nf - 2] for a cell-interior coarse node
-        s = fma(CT::Rb[a * RW + tt], p[f * stride], s);
-      }
-    }
-    out[oidx] = s;
-  }
-}
-
-// First restriction pass, along x0: one thread per coarse cell C writes the k coarse nodes
-// k*C .. k*C+k-1 (every node class, so the band structure is compile-time) from the fine window
-// 2k(C-1) .. 2k(C+1) held in registers.  `in` has extents (o2, o1, nf), `out` (o2, o1, nc); rows
-// on the Dirichlet boundary of the (still fine) other axes are written 0.
-template <int K, typename T>
-__global__ void restrict_x0_kernel(const T* __restrict__ in, T* __restrict__ out, int nf, int nc, int o1, int o2) {
-  constexpr int RW = 4 * K + 1;
-  const int ncc = (nc - 1) / K;  // coarse cells along x0
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;  // (i1, C)
-  if (t >= (ncc + 1) * o1) return;
-  const int i1 = t / (ncc + 1), C = t - i1 * (ncc + 1);
-  using CT = gen::CellTables<T, K>;
-  for (int i2 = blockIdx.y; i2 < o2; i2 += gridDim.y) {
-    const bool row_zero = i1 == 0 || i1 == nf - 1 || (o2 > 1 && (i2 == 0 || i2 == nf - 1));
-    const long long row = (long long)i2 * o1 + i1;
-    T* q = out + row * nc;
-    if (C == ncc) {
-      q[nc - 1] = T(0);
-      continue;
-    }
-    const T* p = in + row * nf;
-    const int f0 = 2 * K * (C - 1);
-    T w[RW];
-#pragma unroll
-    for (int tt = 0; tt < RW; ++tt) {
-      const int f = f0 + tt;
-      const int fc = f < 0 ? 0 : (f > nf - 1 ? nf - 1 : f);
-      const T v = p[fc];
-      w[tt] = (f > 0 && f < nf - 1) ? v : T(0);
-    }
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      T s = T(0);
-#pragma unroll
-      for (int tt = a == 0 ? 0 : 2 * K; tt < RW; ++tt) s = fma_tab(CT::Rb[a * RW + tt], w[tt], s);
-      q[K * C + a] = (row_zero || (a == 0 && C == 0)) ? T(0) : s;
-    }
-  }
-}
-
 // ------------------------------------------------- restriction, 3D in two kernels
 //
 // rc = (P1 x P1 x P1)^T rf in cell form: along each axis the fine nodes are split into
@@ -782,6 +690,80 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
     for (int a = 0; a < K; ++a) {
       const long long gy = o1 + cy * K + a;
       if (gx < nc && gy < nc) out[gy * nc + gx] = restrict_run<K, T>(in, a);
+    }
+  }
+}
+
+// ------------------------------------------------- restriction, 2D in one kernel
+//
+// The in-plane part of the 3D scheme on the whole 2D grid: a workgroup owns a TX x TX coarse tile,
+// loads the fine nodes [2o - 2K, 2o + 2TX - 1] of both axes into LDS (fine boundary nodes as 0),
+// reduces along x0 (cell runs, restrict_run) and then along x1, and writes its coarse nodes, 0 on
+// the coarse boundary.  The tiles cover every coarse node; a non-null xz (the coarse iterate) is
+// zeroed on the same nodes.
+template <int K, typename T>
+struct Res2D {
+  static constexpr int CX = K == 1 ? 28 : K == 2 ? 14 : K == 3 ? 9 : K == 4 ? 7 : K == 5 ? 5 : 4;
+  static constexpr int TX = K * CX;          // coarse nodes per tile side
+  static constexpr int NT = 256;
+  static constexpr int IX = 2 * TX + 2 * K;  // fine extent per side
+  static constexpr int LPT = (IX * IX + NT - 1) / NT;
+  static constexpr int XS = IX | 1;                      // odd row stride of the fine tile
+  static constexpr int RS = TX + (6 - TX % 4) % 4;       // 2 mod 4 row stride of the x0-reduced tile
+};
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void restrict_tile2d_kernel(const T* __restrict__ rf, T* __restrict__ rc,
+                                                             T* __restrict__ xz, long long nf, long long nc,
+                                                             int tiles) {
+  using S = Res2D<K, T>;
+  constexpr int NT = S::NT, TX = S::TX, IX = S::IX, CX = S::CX, RUN = 2 * K, LPT = S::LPT, XS = S::XS, RS = S::RS;
+  __shared__ T X[IX * XS];
+  __shared__ T Rx[IX * RS];
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles, ty = blk / tiles;
+  const long long o0 = (long long)tx * TX, o1 = (long long)ty * TX;
+  const long long fy0 = 2 * o1 - 2 * K, fx0 = 2 * o0 - 2 * K;
+  const int tid = threadIdx.x;
+  T v[LPT];
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) {
+    const int i = tid + l * NT;
+    const int r = i / IX, c = i - r * IX;
+    const long long fy = fy0 + r, fx = fx0 + c;
+    const bool ok = i < IX * IX && fy >= 1 && fy <= nf - 2 && fx >= 1 && fx <= nf - 2;
+    v[l] = ok ? rf[fy * nf + fx] : T(0);
+  }
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) {
+    const int i = tid + l * NT;
+    const int r = i / IX, c = i - r * IX;
+    if (i < IX * IX) X[r * XS + c] = v[l];
+  }
+  __syncthreads();
+  for (int task = tid; task < IX * CX; task += NT) {
+    const int r = task / CX, cx = task - r * CX;
+    T in[2 * RUN];
+#pragma unroll
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = X[r * XS + RUN * cx + t];
+#pragma unroll
+    for (int a = 0; a < K; ++a) Rx[r * RS + cx * K + a] = restrict_run<K, T>(in, a);
+  }
+  __syncthreads();
+  for (int task = tid; task < TX * CX; task += NT) {
+    const int cy = task / TX, c = task - cy * TX;
+    T in[2 * RUN];
+#pragma unroll
+    for (int t = 0; t < 2 * RUN; ++t) in[t] = Rx[(RUN * cy + t) * RS + c];
+    const long long gx = o0 + c;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      const long long gy = o1 + cy * K + a;
+      if (gx < nc && gy < nc) {
+        const bool bnd = gx == 0 || gy == 0 || gx == nc - 1 || gy == nc - 1;
+        rc[gy * nc + gx] = bnd ? T(0) : restrict_run<K, T>(in, a);
+        if (xz) xz[gy * nc + gx] = T(0);
+      }
     }
   }
 }
@@ -1089,7 +1071,7 @@ bool res_fits(const LevelGeom& fine) {
            nc <= 65535 && ncc <= 65535 && nc * nc * (long long)sizeof(T) < (1LL << 32) &&
            ceil_div(ncc, kResCellsPerThread) <= 65535;
   }
-  return (ncc + 1) * nf / 256 < (1LL << 31) && nc * nc / 256 < (1LL << 31);
+  return ceil_div(nc, Res2D<K, T>::TX) * ceil_div(nc, Res2D<K, T>::TX) <= 0x7fffffffLL;
 }
 
 template <int D, int K, typename T>
@@ -1109,15 +1091,9 @@ hipError_t res_launch(const LevelGeom& fine, const void* rf, void* rc, hipStream
                                                       (unsigned)ceil_div(ncc, kResCellsPerThread)),
                        dim3(64, 4), 0, st, (const T*)t, (T*)rc, nf, nc, (T*)xz);
   } else {
-    // grid x: 256-thread blocks over one output plane (rows flattened)
-    hipLaunchKernelGGL((restrict_x0_kernel<K, T>), dim3((unsigned)(((long long)(ncc + 1) * nf + 255) / 256)), dim3(256),
-                       0, st, (const T*)rf, (T*)t, nf, nc, nf, 1);
-    hipLaunchKernelGGL((restrict_pass_kernel<K, T, 1>), dim3((unsigned)(((long long)nc * nc + 255) / 256)), dim3(256),
-                       0, st, (const T*)t, (T*)rc, nf, nc, nc, nc, 1);
-    if (xz) {
-      hipError_t e = launch_fill(sizeof(T) == 8 ? 0 : 1, xz, (long long)nc * nc, 0.0, st);
-      if (e != hipSuccess) return e;
-    }
+    const int tiles = ceil_div(nc, Res2D<K, T>::TX);
+    hipLaunchKernelGGL((restrict_tile2d_kernel<K, T>), dim3((unsigned)(tiles * tiles)), dim3(Res2D<K, T>::NT), 0, st,
+                       (const T*)rf, (T*)rc, (T*)xz, (long long)nf, (long long)nc, tiles);
   }
   return hipGetLastError();
 }
