@@ -61,19 +61,23 @@ __device__ __forceinline__ void load_row(T (&in)[N], const T* __restrict__ row, 
 
 // ----------------------------------------------------------------- operator
 
-// Cells per tile along (x0, x1, x2).
+// Cells per tile along (x0, x1, x2).  2D: a task is one cell of one row (stage x0) or of one
+// column (stage x1), so a tile of C0 x C1 cells has (K (C1 + 1) + 1) C0 and K C0 C1 tasks; the
+// shapes keep K C0 near 64 output columns and both task counts near or above the workgroup size.
 template <int D, int K>
 struct OpShape {
-  static constexpr int C0 = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K <= 4 ? 8 : 4) : (16 / K > 1 ? 16 / K : 1);
-  static constexpr int C1 = D == 2 ? (K == 1 ? 8 : K <= 3 ? 4 : 2) : (K == 1 ? 8 : K <= 4 ? 2 : 1);
+  static constexpr int C0 = D == 2 ? (K == 1 ? 64 : K == 2 ? 32 : K <= 4 ? 16 : K == 5 ? 12 : K == 6 ? 10 : 8)
+                                   : (16 / K > 1 ? 16 / K : 1);
+  static constexpr int C1 = D == 2 ? (K == 1 ? 16 : K <= 3 ? 8 : K == 4 ? 6 : K == 5 ? 5 : 4)
+                                   : (K == 1 ? 8 : K <= 4 ? 2 : 1);
   static constexpr int C2 = D == 3 ? C1 : 1;
-  static constexpr int NT = D == 3 && K <= 4 ? 256 : 128;
+  static constexpr int NT = D == 2 || K <= 4 ? 256 : 128;
 };
 
 template <int D, int K, typename T, bool RESID>
 __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* __restrict__ x, const T* __restrict__ b,
                                                                      T* __restrict__ y, long long n1d, int tiles0,
-                                                                     int tiles1, T scale) {
+                                                                     int tiles1, T scale, double* __restrict__ pq_part) {
   using S = OpShape<D, K>;
   constexpr int NT = S::NT, W = 2 * K + 1;
   constexpr int TO0 = K * S::C0, TO1 = K * S::C1, TO2 = K * S::C2;
@@ -88,60 +92,116 @@ __global__ __launch_bounds__((OpShape<D, K>::NT)) void op_tile_kernel(const T* _
 
   __shared__ T PM[TI2 * TI1 * TO0];
   __shared__ T PA[TI2 * TI1 * TO0];
+  // 2D FP64 x.y partials: x at the tile's output nodes, kept from stage x0
+  constexpr bool XS = D == 2 && sizeof(T) == 8 && !RESID;
+  __shared__ T XO[XS ? TO1 * TO0 : 1];
+  const bool keep_x = XS && pq_part;
 
-  // stage x0: rows (z, y) of the input block
+  // stage x0: rows (z, y) of the input block; 2D: cells of those rows (direct row loads: staging
+  // the block in LDS first measured slower, it costs occupancy)
   const bool xin = o0 - K >= 1 && o0 - K + TI0 - 1 <= n1d - 2;
-  for (int task = tid; task < TI2 * TI1; task += NT) {
-    using CT = gen::CellTables<T, K>;
-    const int zl = task / TI1, yl = task - zl * TI1;
-    const long long gz = D == 3 ? o2 - K + zl : 0, gy = o1 - K + yl;
-    T in[TI0];
-    const bool row_ok = !is_bnd(gy, n1d) && (D == 2 || !is_bnd(gz, n1d));
-    const long long gzc = gz < 0 ? 0 : (gz > n1d - 1 ? n1d - 1 : gz), gyc = gy < 0 ? 0 : (gy > n1d - 1 ? n1d - 1 : gy);
-    load_row<T, TI0>(in, x + (D == 3 ? gzc * n1d2 : 0) + gyc * n1d, o0 - K, n1d, xin, row_ok);
+  if constexpr (D == 2) {
+    for (int task = tid; task < TI1 * S::C0; task += NT) {
+      using CT = gen::CellTables<T, K>;
+      const int yl = task / S::C0, cx = task - yl * S::C0;
+      const long long gy = o1 - K + yl;
+      const long long gyc = gy < 0 ? 0 : (gy > n1d - 1 ? n1d - 1 : gy);
+      // nodes [vertex - K, vertex + K] around the cell's left vertex o0 + cx K
+      T in[W];
+      load_row<T, W>(in, x + gyc * n1d, o0 + cx * K - K, n1d, xin, !is_bnd(gy, n1d));
 #pragma unroll
-    for (int xo = 0; xo < TO0; ++xo) {
-      const int c = xo % K;
-      T sm = T(0), sa = T(0);
+      for (int c = 0; c < K; ++c) {
+        T sm = T(0), sa = T(0);
 #pragma unroll
-      for (int t = 0; t < W; ++t) {
-        if (c > 0 && t < K) continue;
-        sm = fma_tab(CT::Mb[c * W + t], in[xo - c + t], sm);
-        sa = fma_tab(CT::Ab[c * W + t], in[xo - c + t], sa);
+        for (int t = 0; t < W; ++t) {
+          if (c > 0 && t < K) continue;
+          sm = fma_tab(CT::Mb[c * W + t], in[t], sm);
+          sa = fma_tab(CT::Ab[c * W + t], in[t], sa);
+        }
+        PM[yl * TO0 + cx * K + c] = sm;
+        PA[yl * TO0 + cx * K + c] = sa;
       }
-      PM[(zl * TI1 + yl) * TO0 + xo] = sm;
-      PA[(zl * TI1 + yl) * TO0 + xo] = sa;
+      if (keep_x && yl >= K && yl < K + TO1) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) XO[(yl - K) * TO0 + cx * K + c] = in[K + c];
+      }
+    }
+  } else {
+    for (int task = tid; task < TI2 * TI1; task += NT) {
+      using CT = gen::CellTables<T, K>;
+      const int zl = task / TI1, yl = task - zl * TI1;
+      const long long gz = o2 - K + zl, gy = o1 - K + yl;
+      T in[TI0];
+      const bool row_ok = !is_bnd(gy, n1d) && !is_bnd(gz, n1d);
+      const long long gzc = gz < 0 ? 0 : (gz > n1d - 1 ? n1d - 1 : gz), gyc = gy < 0 ? 0 : (gy > n1d - 1 ? n1d - 1 : gy);
+      load_row<T, TI0>(in, x + gzc * n1d2 + gyc * n1d, o0 - K, n1d, xin, row_ok);
+#pragma unroll
+      for (int xo = 0; xo < TO0; ++xo) {
+        const int c = xo % K;
+        T sm = T(0), sa = T(0);
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          if (c > 0 && t < K) continue;
+          sm = fma_tab(CT::Mb[c * W + t], in[xo - c + t], sm);
+          sa = fma_tab(CT::Ab[c * W + t], in[xo - c + t], sa);
+        }
+        PM[(zl * TI1 + yl) * TO0 + xo] = sm;
+        PA[(zl * TI1 + yl) * TO0 + xo] = sa;
+      }
     }
   }
   __syncthreads();
 
   if constexpr (D == 2) {
     // stage x1: columns xo, outputs y = A1 (M1 x) + M1 (A1 x)
-    for (int task = tid; task < TO0; task += NT) {
+    // pq_part (FP64 only): as in the streaming form, the block's partial sum of x_i y_i, or of
+    // (b - A x)_i^2 with the residual not stored
+    double pq = 0.0;
+    for (int task = tid; task < TO0 * S::C1; task += NT) {
       using CT = gen::CellTables<T, K>;
-      const int xo = task;
-      T pm[TI1], pa[TI1];
+      const int cy = task / TO0, xo = task - cy * TO0;
+      // rows [vertex - K, vertex + K] around the cell's lower vertex o1 + cy K
+      T pm[W], pa[W];
 #pragma unroll
-      for (int j = 0; j < TI1; ++j) {
-        pm[j] = PM[j * TO0 + xo];
-        pa[j] = PA[j * TO0 + xo];
+      for (int j = 0; j < W; ++j) {
+        pm[j] = PM[(cy * K + j) * TO0 + xo];
+        pa[j] = PA[(cy * K + j) * TO0 + xo];
       }
       const long long gx = o0 + xo;
 #pragma unroll
-      for (int yo = 0; yo < TO1; ++yo) {
-        const int c = yo % K;
+      for (int c = 0; c < K; ++c) {
+        const int yo = cy * K + c;
         T s = T(0);
 #pragma unroll
         for (int t = 0; t < W; ++t) {
           if (c > 0 && t < K) continue;
-          s = fma_tab(CT::Ab[c * W + t], pm[yo - c + t], s);
-          s = fma_tab(CT::Mb[c * W + t], pa[yo - c + t], s);
+          s = fma_tab(CT::Ab[c * W + t], pm[t], s);
+          s = fma_tab(CT::Mb[c * W + t], pa[t], s);
         }
         const long long gy = o1 + yo;
         if (!is_bnd(gx, n1d) && !is_bnd(gy, n1d)) {
           const long long g = gy * n1d + gx;
-          y[g] = RESID ? b[g] - scale * s : scale * s;
+          const T v = RESID ? b[g] - scale * s : scale * s;
+          if (sizeof(T) == 8 && RESID && pq_part) {
+            pq = fma((double)v, (double)v, pq);
+          } else {
+            y[g] = v;
+            if (keep_x) pq = fma((double)XO[yo * TO0 + xo], (double)v, pq);
+          }
         }
+      }
+    }
+    if constexpr (sizeof(T) == 8) {
+      if (pq_part) {
+        // fixed-order block reduction
+        __shared__ double red[NT];
+        red[tid] = pq;
+        __syncthreads();
+        for (int w = 1; w < NT; w *= 2) {
+          if (tid % (2 * w) == 0 && tid + w < NT) red[tid] += red[tid + w];
+          __syncthreads();
+        }
+        if (tid == 0) pq_part[blockIdx.x] = red[0];
       }
     }
   } else {
@@ -1003,19 +1063,28 @@ bool op_tile_fits(const LevelGeom& g) {
   return t0 * t1 <= 0x7fffffffLL && t0 * t1 * t2 <= 0x7fffffffLL;
 }
 
-template <int D, int K, typename T>
-hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st) {
+template <int D, int K>
+long long op_tile_blocks(const LevelGeom& g) {
   using S = OpShape<D, K>;
-  const int t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1), t2 = D == 3 ? ceil_div(g.ncells, S::C2) : 1;
-  const long long blocks = (long long)t0 * t1 * t2;
+  return (long long)ceil_div(g.ncells, S::C0) * ceil_div(g.ncells, S::C1) * (D == 3 ? ceil_div(g.ncells, S::C2) : 1);
+}
+
+// pq_part != null (2D FP64 only): per-workgroup partial sums, see op_tile_kernel
+template <int D, int K, typename T>
+hipError_t op_tile_launch(const LevelGeom& g, const void* x, const void* b, void* y, hipStream_t st,
+                          double* pq_part = nullptr) {
+  using S = OpShape<D, K>;
+  const int t0 = ceil_div(g.ncells, S::C0), t1 = ceil_div(g.ncells, S::C1);
+  const long long blocks = op_tile_blocks<D, K>(g);
   if (!op_tile_fits<D, K>(g)) return hipErrorInvalidConfiguration;
+  if (pq_part && (D != 2 || sizeof(T) != 8)) return hipErrorInvalidValue;
   const T scale = (T)(D == 3 ? g.h : 1.0);  // A_h = h^(d-2) A_1
   if (b)
     hipLaunchKernelGGL((op_tile_kernel<D, K, T, true>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
-                       (const T*)b, (T*)y, g.n1d, t0, t1, scale);
+                       (const T*)b, (T*)y, g.n1d, t0, t1, scale, pq_part);
   else
     hipLaunchKernelGGL((op_tile_kernel<D, K, T, false>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)x,
-                       (const T*)nullptr, (T*)y, g.n1d, t0, t1, scale);
+                       (const T*)nullptr, (T*)y, g.n1d, t0, t1, scale, pq_part);
   return hipGetLastError();
 }
 
@@ -1195,77 +1264,96 @@ hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const vo
 }
 
 namespace {
-__global__ void sum_parts_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
-  __shared__ double red[256];
+// out[0] = sum of part[0..n) in a fixed order (one workgroup of blockDim.x <= 1024 threads)
+__global__ __launch_bounds__(1024) void sum_parts_kernel(const double* __restrict__ part, int n,
+                                                          double* __restrict__ out) {
+  __shared__ double red[1024];
+  const int nt = blockDim.x, tid = threadIdx.x;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
-  red[threadIdx.x] = s;
+#pragma unroll 8
+  for (int i = tid; i < n; i += nt) s += part[i];
+  red[tid] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (tid == 0) out[0] = red[0];
 }
 
-template <int K>
-hipError_t op_pq_k(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
-                   hipStream_t st, bool* fused) {
-  int t0, cz;
-  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
-  // too many partial sums, or planes beyond 32-bit offsets: the caller takes the unfused path
-  if (blocks > max_parts || !op_stream_fits<K, double>(g)) return hipSuccess;
-  hipError_t e = op_stream_launch<K, double>(g, p, nullptr, q, st, part);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)part, (int)blocks, out);
-  *fused = true;
+hipError_t sum_parts(const double* part, long long n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(n > 4096 ? 1024 : 256), 0, st, part, (int)n, out);
   return hipGetLastError();
 }
 
+// Partial sums the fused forms take on level g (0: no fused form there).  3D: the streaming
+// operator on levels that it serves; 2D: the tile operator.
 template <int K>
-hipError_t res_norm_k(const LevelGeom& g, const double* x, const double* b, double* part, int max_parts,
-                      double* out, hipStream_t st, bool* fused) {
-  int t0, cz;
-  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
-  if (blocks > max_parts || !op_stream_fits<K, double>(g)) return hipSuccess;
-  hipError_t e = op_stream_launch<K, double>(g, x, b, nullptr, st, part);
+long long fused_parts_k(const LevelGeom& g) {
+  if (g.dim == 3) {
+    if (g.ncells < kOpStreamMinCells || !op_stream_fits<K, double>(g)) return 0;
+    int t0, cz;
+    return op_stream_blocks<K>(g, &t0, &cz);
+  }
+  if (!op_tile_fits<2, K>(g)) return 0;
+  return op_tile_blocks<2, K>(g);
+}
+
+long long fused_parts(const LevelGeom& g) {
+  switch (g.k) {
+    case 1: return fused_parts_k<1>(g);
+    case 2: return fused_parts_k<2>(g);
+    case 3: return fused_parts_k<3>(g);
+    case 4: return fused_parts_k<4>(g);
+    case 5: return fused_parts_k<5>(g);
+    case 6: return fused_parts_k<6>(g);
+    case 7: return fused_parts_k<7>(g);
+  }
+  return 0;
+}
+
+// x, b: the operator's input and right-hand side (b null: y = A x with x.y partials; b set: |b - A x|^2
+// partials, y not written)
+template <int K>
+hipError_t fused_op_k(const LevelGeom& g, const double* x, const double* b, double* y, double* part,
+                      hipStream_t st) {
+  if (g.dim == 3) return op_stream_launch<K, double>(g, x, b, y, st, part);
+  return op_tile_launch<2, K, double>(g, x, b, y, st, part);
+}
+
+hipError_t fused_op(const LevelGeom& g, const double* x, const double* b, double* y, double* part, long long max_parts,
+                    double* out, hipStream_t st, bool* fused) {
+  *fused = false;
+  const long long n = fused_parts(g);
+  // no fused form, or more partial sums than the buffer holds: the caller takes the unfused path
+  if (n <= 0 || n > max_parts) return hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
+  switch (g.k) {
+    case 1: e = fused_op_k<1>(g, x, b, y, part, st); break;
+    case 2: e = fused_op_k<2>(g, x, b, y, part, st); break;
+    case 3: e = fused_op_k<3>(g, x, b, y, part, st); break;
+    case 4: e = fused_op_k<4>(g, x, b, y, part, st); break;
+    case 5: e = fused_op_k<5>(g, x, b, y, part, st); break;
+    case 6: e = fused_op_k<6>(g, x, b, y, part, st); break;
+    case 7: e = fused_op_k<7>(g, x, b, y, part, st); break;
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)part, (int)blocks, out);
-  *fused = true;
-  return hipGetLastError();
+  e = sum_parts(part, n, out, st);
+  if (e == hipSuccess) *fused = true;
+  return e;
 }
 }  // namespace
 
-hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part, int max_parts,
-                                 double* out, hipStream_t st, bool* fused) {
-  *fused = false;
-  if (!(g.dim == 3 && g.ncells >= kOpStreamMinCells)) return hipSuccess;
-  switch (g.k) {
-    case 1: return res_norm_k<1>(g, x, b, part, max_parts, out, st, fused);
-    case 2: return res_norm_k<2>(g, x, b, part, max_parts, out, st, fused);
-    case 3: return res_norm_k<3>(g, x, b, part, max_parts, out, st, fused);
-    case 4: return res_norm_k<4>(g, x, b, part, max_parts, out, st, fused);
-    case 5: return res_norm_k<5>(g, x, b, part, max_parts, out, st, fused);
-    case 6: return res_norm_k<6>(g, x, b, part, max_parts, out, st, fused);
-    case 7: return res_norm_k<7>(g, x, b, part, max_parts, out, st, fused);
-  }
-  return hipErrorInvalidValue;
+long long fused_reduction_parts(const LevelGeom& g) { return fused_parts(g); }
+
+hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part,
+                                 long long max_parts, double* out, hipStream_t st, bool* fused) {
+  return fused_op(g, x, b, nullptr, part, max_parts, out, st, fused);
 }
 
-hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
-                              hipStream_t st, bool* fused) {
-  *fused = false;
-  if (!(g.dim == 3 && g.ncells >= kOpStreamMinCells)) return hipSuccess;
-  switch (g.k) {
-    case 1: return op_pq_k<1>(g, p, q, part, max_parts, out, st, fused);
-    case 2: return op_pq_k<2>(g, p, q, part, max_parts, out, st, fused);
-    case 3: return op_pq_k<3>(g, p, q, part, max_parts, out, st, fused);
-    case 4: return op_pq_k<4>(g, p, q, part, max_parts, out, st, fused);
-    case 5: return op_pq_k<5>(g, p, q, part, max_parts, out, st, fused);
-    case 6: return op_pq_k<6>(g, p, q, part, max_parts, out, st, fused);
-    case 7: return op_pq_k<7>(g, p, q, part, max_parts, out, st, fused);
-  }
-  return hipErrorInvalidValue;
+hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, long long max_parts,
+                              double* out, hipStream_t st, bool* fused) {
+  return fused_op(g, p, nullptr, q, part, max_parts, out, st, fused);
 }
 
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st) {

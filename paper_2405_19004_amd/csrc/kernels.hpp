@@ -67,14 +67,17 @@ hipError_t launch_colour_pass(const LevelGeom& g, int prec, int mode, int colour
 
 // grid.hip (interior outputs only)
 hipError_t launch_operator(const LevelGeom& g, int prec, const void* x, const void* b_or_null, void* y, hipStream_t st);
+// Per-workgroup partial sums the two fused operator forms below take on level g (0: no fused
+// form on that level).
+long long fused_reduction_parts(const LevelGeom& g);
 // q = A p in FP64 with out[0] = p.q summed in a fixed order from per-workgroup partials (at most
 // max_parts of them); *fused = false (nothing launched) where that form is not available.
-hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, int max_parts, double* out,
-                              hipStream_t st, bool* fused);
+hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, double* part, long long max_parts,
+                              double* out, hipStream_t st, bool* fused);
 // out[0] = |b - A x|^2 (interior, FP64) summed in a fixed order from per-workgroup partials, the
 // residual itself not stored; *fused = false (nothing launched) where that form is not available.
-hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part, int max_parts,
-                                 double* out, hipStream_t st, bool* fused);
+hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part,
+                                 long long max_parts, double* out, hipStream_t st, bool* fused);
 // Restriction P^T of a fine-level vector (fine boundary entries ignored, coarse boundary written 0);
 // t is scratch of restrict_scratch_elems(fine) elements.  A non-null xc_zero (a coarse-level vector)
 // is set to 0 as well, which saves the V-cycle a fill launch per level.

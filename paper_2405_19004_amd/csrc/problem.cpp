@@ -3,6 +3,7 @@
 // other); all vectors stay resident on the device during a solve (Sec. 3.1).
 #include "problem.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -56,6 +57,12 @@ struct Plan {
   std::vector<size_t> sizes;
 };
 
+// Partial sums of the reductions: the vector reductions' pairs, and on the finest level one per
+// workgroup of the fused operator forms.
+long long partial_count(int dim, int k, int L) {
+  return std::max<long long>(2LL * reduction_parts(), fused_reduction_parts(make_geom(dim, k, L)));
+}
+
 // The allocation plan is the single source of the footprint and of create_problem.
 Plan plan(int dim, int k, int L, unsigned flags) {
   Plan pl;
@@ -86,7 +93,7 @@ Plan plan(int dim, int k, int L, unsigned flags) {
     for (int i = 0; i < (h64 ? 4 : 3); ++i) pl.sizes.push_back(N * 8);
   }
   pl.sizes.push_back(kScCount * 8);
-  pl.sizes.push_back(2 * (size_t)reduction_parts() * 8);
+  pl.sizes.push_back((size_t)partial_count(dim, k, L) * 8);
   pl.sizes.push_back(256);  // flag
   return pl;
 }
@@ -184,6 +191,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
   }
   p->sc = (double*)p->allocs[idx++];
   p->partial = (double*)p->allocs[idx++];
+  p->n_partial = partial_count(dim, k, L);
   p->bad = (int*)p->allocs[idx++];
   if (hipHostMalloc((void**)&p->host_sc, kScCount * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&p->host_bad, sizeof(int), hipHostMallocDefault) != hipSuccess) {
@@ -568,7 +576,7 @@ Status pcg_iterate_launch(Problem* p, int mode, double* x, CgState* cs) {
   (void)mode;
   const long long N = p->lv[p->L].N;
   bool fused = false;
-  VPS_HIP(launch_operator_pq(p->geom(p->L), p->p, p->q, p->partial, 2 * reduction_parts(), p->sc + kScPQ, p->stream,
+  VPS_HIP(launch_operator_pq(p->geom(p->L), p->p, p->q, p->partial, p->n_partial, p->sc + kScPQ, p->stream,
                              &fused));
   if (!fused) {
     VPS_HIP(launch_operator(p->geom(p->L), 0, p->p, nullptr, p->q, p->stream));
@@ -623,9 +631,9 @@ Status pcg_end_launch(Problem* p, const double* b, const double* x, const CgStat
   *pending = false;
   if (cs->stats.status == -6 || cs->bb == 0.0) return Status::ok();
   const long long N = p->lv[p->L].N;
-  // |b - A x|^2 in one pass where the streaming operator serves the level, else through q
+  // |b - A x|^2 in one pass where a fused operator form serves the level, else through q
   bool fused = false;
-  VPS_HIP(launch_residual_norm2(p->geom(p->L), x, b, p->partial, 2 * reduction_parts(), p->sc + kScTrue, p->stream,
+  VPS_HIP(launch_residual_norm2(p->geom(p->L), x, b, p->partial, p->n_partial, p->sc + kScTrue, p->stream,
                                 &fused));
   if (!fused) {
     VPS_HIP(launch_operator(p->geom(p->L), 0, x, b, p->q, p->stream));  // q = b - A x (interior)

@@ -35,7 +35,8 @@ struct Problem {
   // CG state
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double* sc = nullptr;       // scalar block (kScCount doubles)
-  double* partial = nullptr;  // 2 * reduction_parts() doubles
+  double* partial = nullptr;  // n_partial doubles: the reductions' partial sums
+  long long n_partial = 0;    // max(2 * reduction_parts(), fused_reduction_parts(finest level))
   int* bad = nullptr;
   double* host_sc = nullptr;  // pinned mirror of sc
   int* host_bad = nullptr;
