@@ -505,14 +505,15 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
 
 // ----------------------------------------------------------- prolongation
 
-// Coarse cells per tile.
 // Coarse cells per tile and threads: 3D tiles of degree <= 4 span 2kC ~ 16 fine nodes per axis, so
 // the last stage (one thread per fine column) fills a 256-thread workgroup (measured at k = 4:
-// 31 us against 44 us for C = 1 with 128 threads on 64^3 cells).
+// 31 us against 44 us for C = 1 with 128 threads on 64^3 cells).  2D: a task is one coarse cell
+// of one row (stage x0) or of one fine column (stage x1), tiles span 2kC ~ 64 fine nodes.
 template <int D, int K>
 struct ProShape {
-  static constexpr int C = D == 2 ? (K == 1 ? 16 : K == 2 ? 8 : 4) : (K == 1 ? 8 : K == 2 ? 4 : K <= 4 ? 2 : 1);
-  static constexpr int NT = D == 3 && K <= 4 ? 256 : 128;
+  static constexpr int C = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K <= 4 ? 8 : 4)
+                                  : (K == 1 ? 8 : K == 2 ? 4 : K <= 4 ? 2 : 1);
+  static constexpr int NT = D == 2 || K <= 4 ? 256 : 128;
 };
 
 // x_fine += P e_coarse.  Tile: coarse cells [C t, C (t+1)) per axis, fine outputs
@@ -530,110 +531,140 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
   const int tid = threadIdx.x;
   const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
   __shared__ T T1[TIz * TI * TO];
-  // stage x0: coarse rows
-  for (int task = tid; task < TIz * TI; task += NT) {
-    using CT = gen::CellTables<T, K>;
-    const int zl = task / TI, yl = task - zl * TI;
-    const long long gz = D == 3 ? c2 + zl : 0, gy = c1 + yl;
-    const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && (D == 2 || (gz < n1dc && !is_bnd(gz, n1dc)));
-    // every load of the row first, at indices clamped into the grid; out-of-range values taken as 0
-    const long long row = (D == 3 ? min(gz, n1dc - 1) * nc2 : 0) + min(gy, n1dc - 1) * n1dc;
-    T in[TI];
+  if constexpr (D == 2) {
+    // stage x0: coarse cells cc of coarse rows yl
+    for (int task = tid; task < TI * C; task += NT) {
+      using CT = gen::CellTables<T, K>;
+      const int yl = task / C, cc = task - yl * C;
+      const long long gy = c1 + yl;
+      const bool ok = gy < n1dc && !is_bnd(gy, n1dc);
+      const long long row = min(gy, n1dc - 1) * n1dc;
+      T in[NP];
 #pragma unroll
-    for (int j = 0; j < TI; ++j) in[j] = e[row + min(c0 + j, n1dc - 1)];
-#pragma unroll
-    for (int j = 0; j < TI; ++j) {
-      const long long gx = c0 + j;
-      if (!(ok && gx < n1dc && !is_bnd(gx, n1dc))) in[j] = T(0);
-    }
-#pragma unroll
-    for (int xo = 0; xo < TO; ++xo) {
-      const int cc = xo / (2 * K), q = xo % (2 * K);
-      T s = T(0);
+      for (int a = 0; a < NP; ++a) in[a] = e[row + min(c0 + K * cc + a, n1dc - 1)];
 #pragma unroll
       for (int a = 0; a < NP; ++a) {
-        if (q == 0 && a > 0) continue;
-        s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
-      }
-      T1[(zl * TI + yl) * TO + xo] = s;
-    }
-  }
-  __syncthreads();
-  if constexpr (D == 2) {
-    for (int task = tid; task < TO; task += NT) {
-      using CT = gen::CellTables<T, K>;
-      const int xo = task;
-      T in[TI];
-#pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T1[j * TO + xo];
-      const long long gx = f0 + xo;
-      T old[TO];  // own outputs: all loads before the first store
-#pragma unroll
-      for (int yo = 0; yo < TO; ++yo) {
-        const long long gy = f1 + yo;
-        old[yo] = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df) ? xf[gy * n1df + gx] : T(0);
+        const long long gx = c0 + K * cc + a;
+        if (!(ok && gx < n1dc && !is_bnd(gx, n1dc))) in[a] = T(0);
       }
 #pragma unroll
-      for (int yo = 0; yo < TO; ++yo) {
-        const int cc = yo / (2 * K), q = yo % (2 * K);
+      for (int q = 0; q < 2 * K; ++q) {
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
-          s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
+          s = fma_tab(CT::P[q * NP + a], in[a], s);
         }
-        const long long gy = f1 + yo;
-        if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] = old[yo] + s;
-      }
-    }
-  } else {
-    __shared__ T T2[TI * TO * TO];
-    for (int task = tid; task < TI * TO; task += NT) {
-      using CT = gen::CellTables<T, K>;
-      const int zl = task / TO, xo = task - zl * TO;
-      T in[TI];
-#pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T1[(zl * TI + j) * TO + xo];
-#pragma unroll
-      for (int yo = 0; yo < TO; ++yo) {
-        const int cc = yo / (2 * K), q = yo % (2 * K);
-        T s = T(0);
-#pragma unroll
-        for (int a = 0; a < NP; ++a) {
-          if (q == 0 && a > 0) continue;
-          s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
-        }
-        T2[(zl * TO + yo) * TO + xo] = s;
+        T1[yl * TO + 2 * K * cc + q] = s;
       }
     }
     __syncthreads();
-    for (int task = tid; task < TO * TO; task += NT) {
+    // stage x1: coarse cells cc of fine columns xo; the thread's outputs are its own, every old value
+    // is loaded before the first store
+    for (int task = tid; task < TO * C; task += NT) {
       using CT = gen::CellTables<T, K>;
-      const int yo = task / TO, xo = task - yo * TO;
-      T in[TI];
+      const int cc = task / TO, xo = task - cc * TO;
+      T in[NP];
 #pragma unroll
-      for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
-      const long long gx = f0 + xo, gy = f1 + yo;
-      const bool ok = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df);
-      // the thread's outputs are its own (tiles do not overlap): every old value is loaded before
-      // the first store, so the loads are in flight together instead of one after each store
-      T old[TO];
+      for (int a = 0; a < NP; ++a) in[a] = T1[(K * cc + a) * TO + xo];
+      const long long gx = f0 + xo;
+      T old[2 * K];
 #pragma unroll
-      for (int zo = 0; zo < TO; ++zo) {
-        const long long gz = f2 + zo;
-        old[zo] = ok && gz < n1df && !is_bnd(gz, n1df) ? xf[gz * nf2 + gy * n1df + gx] : T(0);
+      for (int q = 0; q < 2 * K; ++q) {
+        const long long gy = f1 + 2 * K * cc + q;
+        old[q] = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df) ? xf[gy * n1df + gx] : T(0);
       }
 #pragma unroll
-      for (int zo = 0; zo < TO; ++zo) {
-        const int cc = zo / (2 * K), q = zo % (2 * K);
+      for (int q = 0; q < 2 * K; ++q) {
+        T s = T(0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          if (q == 0 && a > 0) continue;
+          s = fma_tab(CT::P[q * NP + a], in[a], s);
+        }
+        const long long gy = f1 + 2 * K * cc + q;
+        if (gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df)) xf[gy * n1df + gx] = old[q] + s;
+      }
+    }
+  } else {
+    // stage x0: coarse rows
+    for (int task = tid; task < TIz * TI; task += NT) {
+      using CT = gen::CellTables<T, K>;
+      const int zl = task / TI, yl = task - zl * TI;
+      const long long gz = c2 + zl, gy = c1 + yl;
+      const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && gz < n1dc && !is_bnd(gz, n1dc);
+      // every load of the row first, at indices clamped into the grid; out-of-range values taken as 0
+      const long long row = min(gz, n1dc - 1) * nc2 + min(gy, n1dc - 1) * n1dc;
+      T in[TI];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) in[j] = e[row + min(c0 + j, n1dc - 1)];
+#pragma unroll
+      for (int j = 0; j < TI; ++j) {
+        const long long gx = c0 + j;
+        if (!(ok && gx < n1dc && !is_bnd(gx, n1dc))) in[j] = T(0);
+      }
+#pragma unroll
+      for (int xo = 0; xo < TO; ++xo) {
+        const int cc = xo / (2 * K), q = xo % (2 * K);
         T s = T(0);
 #pragma unroll
         for (int a = 0; a < NP; ++a) {
           if (q == 0 && a > 0) continue;
           s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
         }
-        const long long gz = f2 + zo;
-        if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] = old[zo] + s;
+        T1[(zl * TI + yl) * TO + xo] = s;
+      }
+    }
+    __syncthreads();
+    {
+      __shared__ T T2[TI * TO * TO];
+      for (int task = tid; task < TI * TO; task += NT) {
+        using CT = gen::CellTables<T, K>;
+        const int zl = task / TO, xo = task - zl * TO;
+        T in[TI];
+#pragma unroll
+        for (int j = 0; j < TI; ++j) in[j] = T1[(zl * TI + j) * TO + xo];
+#pragma unroll
+        for (int yo = 0; yo < TO; ++yo) {
+          const int cc = yo / (2 * K), q = yo % (2 * K);
+          T s = T(0);
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            if (q == 0 && a > 0) continue;
+            s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
+          }
+          T2[(zl * TO + yo) * TO + xo] = s;
+        }
+      }
+      __syncthreads();
+      for (int task = tid; task < TO * TO; task += NT) {
+        using CT = gen::CellTables<T, K>;
+        const int yo = task / TO, xo = task - yo * TO;
+        T in[TI];
+#pragma unroll
+        for (int j = 0; j < TI; ++j) in[j] = T2[(j * TO + yo) * TO + xo];
+        const long long gx = f0 + xo, gy = f1 + yo;
+        const bool ok = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df);
+        // the thread's outputs are its own (tiles do not overlap): every old value is loaded before
+        // the first store, so the loads are in flight together instead of one after each store
+        T old[TO];
+#pragma unroll
+        for (int zo = 0; zo < TO; ++zo) {
+          const long long gz = f2 + zo;
+          old[zo] = ok && gz < n1df && !is_bnd(gz, n1df) ? xf[gz * nf2 + gy * n1df + gx] : T(0);
+        }
+#pragma unroll
+        for (int zo = 0; zo < TO; ++zo) {
+          const int cc = zo / (2 * K), q = zo % (2 * K);
+          T s = T(0);
+#pragma unroll
+          for (int a = 0; a < NP; ++a) {
+            if (q == 0 && a > 0) continue;
+            s = fma_tab(CT::P[q * NP + a], in[K * cc + a], s);
+          }
+          const long long gz = f2 + zo;
+          if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] = old[zo] + s;
+        }
       }
     }
   }
