@@ -277,6 +277,34 @@ def table7_run(v, torch):
     return rows
 
 
+def solve_2d_q7_run(v, torch, reps=5):
+    """2D Q7 on 512^2 cells (12.8M DoFs), manufactured solution sin(pi x) sin(pi y), mixed and FP64
+    CG with the V-cycle of the bench step, to 1e-10: solve time with the rhs resident, iterations,
+    true residual and L2 error of the discrete solution."""
+    import synth
+    kap, co = synth.manufactured_sine(2)
+    uc = [c / (math.pi ** 2 * sum(q * q for q in kk)) for kk, c in zip(kap, co)]
+    P = v.Problem(2, 7, 9, v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY | v.VPS_FLAG_POST_SAME_ORDER)
+    b = P.rhs_sine_modes(kap, co)
+    x = P.new()
+    out = {"workload": "2D Poisson Q7, 512^2 cells, u = sin(pi x) sin(pi y), CG to 1e-10", "n_dofs": P.n()}
+    for name, mode in (("mixed", v.VPS_SOLVE_MIXED), ("fp64", v.VPS_SOLVE_FP64)):
+        P.pcg_solve(b, x, 1e-10, 100, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, st = P.pcg_solve(b, x, 1e-10, 100, mode)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        out[name] = {"ms": ms, "dof_per_s": P.n() / (ms / 1e3), "iterations": st.iterations,
+                     "true_rel_residual": st.true_rel_residual, "l2_error": P.l2_error_sine_modes(x, kap, uc)}
+    out["mixed_speedup"] = out["fp64"]["ms"] / out["mixed"]["ms"]
+    del b, x
+    P.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def fmg_run(v, torch, P, kap, co):
     """Full multigrid on the bench problem (right-hand side on every level), both precisions."""
     res = {}
@@ -539,6 +567,9 @@ def main():
                                         "alu_tflops": flops / t64 / 1e12, "alu_frac": flops / t64 / PEAK_FP64}
     P.close()
     progress("headline solve, components and colour-pass roofline done")
+
+    out["solve_2d_q7"] = solve_2d_q7_run(v, torch)
+    progress("2D Q7 solves done")
 
     if a.serve > 0:
         out["serving"] = serving_run(v, a.serve, max_active=a.serve_slots)

@@ -164,9 +164,9 @@ int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, v
  * VPS_FP64, FP32 when VPS_FP32; both caller-owned.  hip_stream: the stream the launches go to
  * (NULL: the null stream); nothing synchronises.  The intermediate lives in a static device
  * array of 64 MiB per GPU held until the process ends, shared by every call on that GPU: calls
- * that overlap on one GPU race.  VPS_EINVAL when the intermediate (n1d(fine)^(dim-1) *
- * n1d(fine-1) values of the precision's size in 3D, n1d(fine) * n1d(fine-1) in 2D) exceeds it,
- * on a bad shape or precision, or on a null vector; VPS_EHIP on a launch failure. */
+ * that overlap on one GPU race.  VPS_EINVAL when the intermediate (3D: n1d(fine)^2 *
+ * n1d(fine-1) values of the precision's size; the 2D restriction has none) exceeds it, on a bad
+ * shape or precision, or on a null vector; VPS_EHIP on a launch failure. */
 int vps_restrict_noalloc(int dim, int degree, int fine_level, int prec, const void* r_fine, void* r_coarse,
                          void* hip_stream);
 

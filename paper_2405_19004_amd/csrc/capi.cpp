@@ -268,7 +268,7 @@ int vps_restrict(vps_problem* p, int fine_level, int prec, const void* r_fine, v
     if (int e = check_prec(prec)) return e;
     if (!r_fine || !r_coarse) return fail(VPS_EINVAL, "null vector");
     const vps::LevelBuffers& B = p->impl->lv[fine_level];
-    if (!B.t[prec]) return fail(VPS_EINVAL, "restriction in this precision needs the matching hierarchy flag");
+    if (!B.r[prec]) return fail(VPS_EINVAL, "restriction in this precision needs the matching hierarchy flag");
     hipError_t e = vps::launch_restrict(p->impl->geom(fine_level), prec, r_fine, r_coarse, B.t[prec],
                                         p->impl->stream);
     return e == hipSuccess ? VPS_OK : fail(VPS_EHIP, std::string("restrict launch: ") + hipGetErrorString(e));

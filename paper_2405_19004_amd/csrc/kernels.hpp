@@ -79,13 +79,14 @@ hipError_t launch_operator_pq(const LevelGeom& g, const double* p, double* q, do
 hipError_t launch_residual_norm2(const LevelGeom& g, const double* x, const double* b, double* part,
                                  long long max_parts, double* out, hipStream_t st, bool* fused);
 // Restriction P^T of a fine-level vector (fine boundary entries ignored, coarse boundary written 0);
-// t is scratch of restrict_scratch_elems(fine) elements.  A non-null xc_zero (a coarse-level vector)
-// is set to 0 as well, which saves the V-cycle a fill launch per level.
+// t is scratch of restrict_scratch_elems(fine) elements (none in 2D: one kernel, no intermediate).
+// A non-null xc_zero (a coarse-level vector) is set to 0 as well, which saves the V-cycle a fill
+// launch per level.
 hipError_t launch_restrict(const LevelGeom& fine, int prec, const void* rf, void* rc, void* t, hipStream_t st,
                            void* xc_zero = nullptr);
 inline long long restrict_scratch_elems(int dim, int k, int fine_level) {
   const long long nf = (long long)k * (1LL << fine_level) + 1, nc = (long long)k * (1LL << (fine_level - 1)) + 1;
-  return dim == 2 ? nf * nc : nf * nc * nc;
+  return dim == 2 ? 0 : nf * nc * nc;
 }
 hipError_t launch_prolongate_add(const LevelGeom& fine, int prec, const void* e, void* xf, hipStream_t st);
 // The allocation-free restriction's scratch: a static device array of noalloc_scratch_bytes()

@@ -79,7 +79,7 @@ Plan plan(int dim, int k, int L, unsigned flags) {
         pl.sizes.push_back(N * es);  // x
       }
       pl.sizes.push_back(N * es);  // r (V-cycle residual; the Separate smoother's residual on every level)
-      if (lvl >= 2) pl.sizes.push_back((size_t)restrict_scratch_elems(dim, k, lvl) * es);  // restriction scratch
+      if (lvl >= 2 && dim == 3) pl.sizes.push_back((size_t)restrict_scratch_elems(dim, k, lvl) * es);  // restriction scratch
     }
   }
   if (h32) {
@@ -176,7 +176,7 @@ Status create_problem(int dim, int k, int L, unsigned flags, hipStream_t st, Pro
         B.x[prec] = p->allocs[idx++];
       }
       B.r[prec] = p->allocs[idx++];
-      if (lvl >= 2) B.t[prec] = p->allocs[idx++];
+      if (lvl >= 2 && dim == 3) B.t[prec] = p->allocs[idx++];
     }
   }
   if (h32) {

@@ -22,7 +22,7 @@ struct LevelBuffers {
   void* b[2] = {nullptr, nullptr};  // V-cycle right-hand side per precision (levels < L; FP32 also L)
   void* x[2] = {nullptr, nullptr};  // V-cycle iterate per precision
   void* r[2] = {nullptr, nullptr};  // residual per precision (every level)
-  void* t[2] = {nullptr, nullptr};  // restriction scratch per precision (levels >= 2)
+  void* t[2] = {nullptr, nullptr};  // restriction scratch per precision (3D levels >= 2)
 };
 
 struct Problem {
