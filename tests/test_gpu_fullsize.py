@@ -14,7 +14,8 @@ the FP64 oracle, element by element:
     interiors must be unchanged bit for bit.  Boundary entries of x and b are NaN:
     the kernels must never read them;
   * operator apply and residual in the streaming form (3D, 32 cells and up, every
-    degree; 3D Q4 64^3; 2D Q7 512^2), FP64 and FP32;
+    degree; 3D Q4 64^3; 2D Q7 512^2), and the 2D tile form with several tiles per
+    axis for every degree, ragged and exact, FP64 and FP32;
   * restriction and prolongation with several tiles per axis, ragged and exact.
 
 Bars (max-abs error over the compared entries, relative to the max-abs reference
@@ -137,7 +138,10 @@ def test_colour_pass_every_patch(d, k, L, prec):
 
 # ------------------------------------------------------------------ operator and residual
 
-OP_CASES = [(3, 1, 5), (3, 2, 5), (3, 3, 5), (3, 4, 5), (3, 5, 5), (3, 6, 5), (3, 7, 5), (3, 4, 6), (2, 7, 9)]
+# 2D tiles hold (64, 32, 16, 16, 12, 10, 8) x (16, 8, 8, 6, 5, 4, 4) cells for K = 1..7: the 2D levels
+# below give 2..8 tiles per axis, ragged along x1 for K = 4, 5 and along x0 for K = 5, 6.
+OP_CASES = [(3, 1, 5), (3, 2, 5), (3, 3, 5), (3, 4, 5), (3, 5, 5), (3, 6, 5), (3, 7, 5), (3, 4, 6), (2, 7, 9),
+            (2, 1, 7), (2, 2, 6), (2, 3, 6), (2, 4, 5), (2, 5, 5), (2, 6, 5), (2, 7, 5)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -168,8 +172,10 @@ def test_operator_and_residual_streaming(d, k, L, prec):
 # levels give 2..8 tiles per axis, ragged (3D Q3, Q5) and exact multiples (the others).  In FP32 the
 # plane pass takes two fine planes per workgroup, and the number of interior fine planes is odd, so
 # its last group is partial at every level.
+# 2D prolongation tiles hold (32, 16, 8, 8, 4, 4, 4) coarse cells per axis for K = 1..7: the 2D
+# levels below give 2..8 tiles per axis.
 TRANSFER_CASES = [(3, 1, 6), (3, 2, 5), (3, 3, 5), (3, 4, 4), (3, 4, 6), (3, 5, 4), (3, 6, 4), (3, 7, 4),
-                  (3, 7, 5), (2, 3, 7), (2, 7, 6)]
+                  (3, 7, 5), (2, 3, 7), (2, 7, 6), (2, 1, 7), (2, 2, 6), (2, 4, 6), (2, 5, 5), (2, 6, 5)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
