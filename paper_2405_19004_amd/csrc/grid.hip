@@ -1044,13 +1044,22 @@ namespace {
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-template <int K>
+// Workgroups the streaming operator aims for: 2048, except FP64 at degrees 4 and 7, where fewer,
+// longer chunks measured faster (3D Q4 64^3 apply 101 -> 93 us with 1024, mixed solve -0.8%;
+// Q7 32^3 210 -> 184 us with 512).  Degrees 2 and 3 measured slower that way, degree 5 equal and
+// degree 6 gave a faster apply but a slower solve.
+template <int K, typename T>
+constexpr long long op_stream_target() {
+  return sizeof(T) == 8 && K == 4 ? 1024 : sizeof(T) == 8 && K == 7 ? 512 : 2048;
+}
+template <int K, typename T>
 long long op_stream_blocks(const LevelGeom& g, int* t0_out, int* cz_out) {
   using S = OpStream<K>;
   const int t0 = ceil_div(g.ncells, S::CX);
   // enough workgroups to fill the chip, chunks of at least 4 cells along x2
   const long long tiles = (long long)t0 * t0;
-  long long chunks = (2048 + tiles - 1) / tiles;
+  const long long target = op_stream_target<K, T>();
+  long long chunks = (target + tiles - 1) / tiles;
   if (chunks > g.ncells / 4) chunks = g.ncells / 4;
   if (chunks < 1) chunks = 1;
   const int cz = (int)((g.ncells + chunks - 1) / chunks);
@@ -1073,7 +1082,7 @@ hipError_t op_stream_launch(const LevelGeom& g, const void* x, const void* b, vo
   using S = OpStream<K>;
   if (!op_stream_fits<K, T>(g)) return hipErrorInvalidConfiguration;
   int t0, cz;
-  const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
+  const long long blocks = op_stream_blocks<K, T>(g, &t0, &cz);
   if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   const T scale = (T)g.h;  // A_h = h A_1 in 3D
   if (b)
@@ -1247,7 +1256,7 @@ bool grid_launches_ok(const LevelGeom& g, std::string* why) {
   if (D == 3 && g.ncells >= kOpStreamMinCells && op_stream_fits<K, T>(g)) {
     using S = OpStream<K>;
     int t0 = 0, cz = 0;
-    const long long blocks = op_stream_blocks<K>(g, &t0, &cz);
+    const long long blocks = op_stream_blocks<K, T>(g, &t0, &cz);
     const long long tiles = (long long)t0 * t0, chunks = tiles > 0 ? blocks / tiles : 0;
     if (blocks > 0x7fffffffLL) return *why = tag + "streaming operator: grid too large", false;
     if ((long long)t0 * S::CX < g.ncells || chunks * cz < g.ncells)
@@ -1324,7 +1333,7 @@ long long fused_parts_k(const LevelGeom& g) {
   if (g.dim == 3) {
     if (g.ncells < kOpStreamMinCells || !op_stream_fits<K, double>(g)) return 0;
     int t0, cz;
-    return op_stream_blocks<K>(g, &t0, &cz);
+    return op_stream_blocks<K, double>(g, &t0, &cz);
   }
   if (!op_tile_fits<2, K>(g)) return 0;
   return op_tile_blocks<2, K>(g);
