@@ -112,6 +112,8 @@ def parse():
     ap.add_argument("--no-table7", action="store_true",
                     help="skip the mixed/double solves at the sizes of Table 7 (135M-721M DoFs)")
     ap.add_argument("--quick", action="store_true", help="only the timed solves (for profiling)")
+    ap.add_argument("--quick-2d", action="store_true",
+                    help="only the 2D Q7 512^2 solves, mixed and FP64 (for profiling)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the closed-loop mixed serving run of --serve requests (for profiling)")
     ap.add_argument("--serve-slots", type=int, default=16, help="requests the server keeps active at once")
@@ -436,6 +438,9 @@ def main():
         return
     if a.serve_only:
         print(json.dumps(serving_run(v, a.serve, max_active=a.serve_slots, closed_loop_only=not a.serve_replays)))
+        return
+    if a.quick_2d:
+        print(json.dumps({"solve_2d_q7": solve_2d_q7_run(v, torch)}))
         return
     FL = v.VPS_FLAG_FP64_HIERARCHY | v.VPS_FLAG_FP32_HIERARCHY
     P = v.Problem(D, K, L, FL | v.VPS_FLAG_POST_SAME_ORDER)
