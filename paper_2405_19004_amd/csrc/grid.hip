@@ -505,9 +505,9 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
 
 // ----------------------------------------------------------- prolongation
 
-// Coarse cells per tile and threads: 3D tiles of degree <= 4 span 2kC ~ 16 fine nodes per axis, so
-// the last stage (one thread per fine column) fills a 256-thread workgroup (measured at k = 4:
-// 31 us against 44 us for C = 1 with 128 threads on 64^3 cells).  2D: a task is one coarse cell
+// Coarse cells per tile and threads: 3D cubic tiles (degree 1 only; the other degrees take the
+// tiles of prolong3_kernel below) span 2kC ~ 16 fine nodes per axis, so the last stage (one thread
+// per fine column) fills a 256-thread workgroup.  2D: a task is one coarse cell
 // of one row (stage x0) or of one fine column (stage x1), tiles span 2kC ~ 64 fine nodes.
 template <int D, int K>
 struct ProShape {
@@ -668,6 +668,113 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
       }
     }
   }
+}
+
+// 3D prolongation, tiles of C0 x C1 x C2 coarse cells: about 32 fine nodes along x0, 16 along x1
+// and 8 along x2, so that the last stage reads and writes whole 128-byte row segments of x_fine.
+// Every stage takes one coarse cell per task (its K+1 inputs, 2K outputs): one cell of a coarse
+// row (x0), of a fine column along x1 (x1) and along x2 (x2).  Same arithmetic per output as the
+// per-row form, in the same order.  Used for degrees >= 2 (3D Q4 64^3 solve -0.4%, degrees 2, 3
+// and 7 equal); degree 1 measured slower (V-cycle +1.4% at 256^3 cells) and keeps the cubic tiles.
+template <int K>
+constexpr bool kPro3Tiles = K >= 2;
+template <int K>
+struct Pro3 {
+  static constexpr int C0 = K == 1 ? 16 : K == 2 ? 8 : K == 3 ? 5 : K == 4 ? 4 : K <= 6 ? 3 : 2;
+  static constexpr int C1 = K == 1 ? 8 : K == 2 ? 4 : K == 3 ? 3 : K <= 5 ? 2 : 1;
+  static constexpr int C2 = K == 1 ? 4 : K == 2 ? 2 : 1;
+  static constexpr int NT = 256;
+};
+
+template <int K, typename T>
+__global__ __launch_bounds__(256) void prolong3_kernel(const T* __restrict__ e, T* __restrict__ xf, long long n1dc,
+                                                       long long n1df, int tiles0, int tiles1) {
+  using S = Pro3<K>;
+  constexpr int NT = S::NT, NP = K + 1, R = 2 * K;
+  constexpr int TO0 = R * S::C0, TO1 = R * S::C1, TO2 = R * S::C2;
+  constexpr int TI1 = K * S::C1 + 1, TI2 = K * S::C2 + 1;
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = blk % tiles0, ty = (blk / tiles0) % tiles1, tz = blk / (tiles0 * tiles1);
+  const long long c0 = (long long)tx * K * S::C0, c1 = (long long)ty * K * S::C1, c2 = (long long)tz * K * S::C2;
+  const long long f0 = 2 * c0, f1 = 2 * c1, f2 = 2 * c2;
+  const int tid = threadIdx.x;
+  const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
+  __shared__ T T1[TI2 * TI1 * TO0];  // along x0: [coarse z][coarse y][fine x]
+  __shared__ T T2[TI2 * TO1 * TO0];  // along x1: [coarse z][fine y][fine x]
+  using CT = gen::CellTables<T, K>;
+  for (int task = tid; task < TI2 * TI1 * S::C0; task += NT) {
+    const int row = task / S::C0, cc = task - row * S::C0;
+    const int zl = row / TI1, yl = row - zl * TI1;
+    const long long gz = c2 + zl, gy = c1 + yl;
+    const bool ok = gy < n1dc && !is_bnd(gy, n1dc) && gz < n1dc && !is_bnd(gz, n1dc);
+    // every load first, at indices clamped into the grid; out-of-range values taken as 0
+    const long long base = min(gz, n1dc - 1) * nc2 + min(gy, n1dc - 1) * n1dc;
+    T in[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) in[a] = e[base + min(c0 + K * cc + a, n1dc - 1)];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      const long long gx = c0 + K * cc + a;
+      if (!(ok && gx < n1dc && !is_bnd(gx, n1dc))) in[a] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        if (q == 0 && a > 0) continue;
+        s = fma_tab(CT::P[q * NP + a], in[a], s);
+      }
+      T1[row * TO0 + R * cc + q] = s;
+    }
+  }
+  __syncthreads();
+  for (int task = tid; task < TI2 * S::C1 * TO0; task += NT) {
+    const int col = task / TO0, xo = task - col * TO0;
+    const int zl = col / S::C1, cc = col - zl * S::C1;
+    T in[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) in[a] = T1[(zl * TI1 + K * cc + a) * TO0 + xo];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        if (q == 0 && a > 0) continue;
+        s = fma_tab(CT::P[q * NP + a], in[a], s);
+      }
+      T2[(zl * TO1 + R * cc + q) * TO0 + xo] = s;
+    }
+  }
+  __syncthreads();
+  for (int task = tid; task < S::C2 * TO1 * TO0; task += NT) {
+    const int col = task / TO0, xo = task - col * TO0;
+    const int cc = col / TO1, yo = col - cc * TO1;
+    T in[NP];
+#pragma unroll
+    for (int a = 0; a < NP; ++a) in[a] = T2[((K * cc + a) * TO1 + yo) * TO0 + xo];
+    const long long gx = f0 + xo, gy = f1 + yo;
+    const bool ok = gx < n1df && gy < n1df && !is_bnd(gx, n1df) && !is_bnd(gy, n1df);
+    // the thread's outputs are its own: every old value is loaded before the first store
+    T old[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const long long gz = f2 + R * cc + q;
+      old[q] = ok && gz < n1df && !is_bnd(gz, n1df) ? xf[gz * nf2 + gy * n1df + gx] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        if (q == 0 && a > 0) continue;
+        s = fma_tab(CT::P[q * NP + a], in[a], s);
+      }
+      const long long gz = f2 + R * cc + q;
+      if (ok && gz < n1df && !is_bnd(gz, n1df)) xf[gz * nf2 + gy * n1df + gx] = old[q] + s;
+    }
+  }
+  static_assert(TO2 == R * S::C2, "tile extent along x2");
 }
 
 // ------------------------------------------------- restriction, 3D in two kernels
@@ -1147,19 +1254,33 @@ hipError_t op_launch(const LevelGeom& g, const void* x, const void* b, void* y, 
 
 template <int D, int K>
 bool pro_fits(const LevelGeom& fine) {
+  const long long ncc = fine.ncells / 2;
+  if (D == 3 && kPro3Tiles<K>) {
+    using S = Pro3<K>;
+    const long long t0 = ceil_div(ncc, S::C0), t1 = ceil_div(ncc, S::C1), t2 = ceil_div(ncc, S::C2);
+    return t0 * t1 <= 0x7fffffffLL && t0 * t1 * t2 <= 0x7fffffffLL;
+  }
   using S = ProShape<D, K>;
-  const long long tiles = ceil_div(fine.ncells / 2, S::C);
+  const long long tiles = ceil_div(ncc, S::C);
   return tiles <= 0x7fffffffLL && tiles * tiles * (D == 3 ? tiles : 1) <= 0x7fffffffLL;
 }
 
 template <int D, int K, typename T>
 hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_t st) {
-  using S = ProShape<D, K>;
   const long long ncc = fine.ncells / 2;
-  const int tiles = ceil_div(ncc, S::C);
-  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
   const long long n1dc = (long long)K * ncc + 1;
   if (!pro_fits<D, K>(fine)) return hipErrorInvalidConfiguration;
+  if (D == 3 && kPro3Tiles<K>) {
+    using S = Pro3<K>;
+    const int t0 = ceil_div(ncc, S::C0), t1 = ceil_div(ncc, S::C1), t2 = ceil_div(ncc, S::C2);
+    const long long blocks = (long long)t0 * t1 * t2;
+    hipLaunchKernelGGL((prolong3_kernel<K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf, n1dc,
+                       fine.n1d, t0, t1);
+    return hipGetLastError();
+  }
+  using S = ProShape<D, K>;
+  const int tiles = ceil_div(ncc, S::C);
+  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
   hipLaunchKernelGGL((prolong_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf,
                      n1dc, fine.n1d, tiles);
   return hipGetLastError();
