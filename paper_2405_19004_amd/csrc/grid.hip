@@ -62,12 +62,13 @@ __device__ __forceinline__ void load_row(T (&in)[N], const T* __restrict__ row, 
 // ----------------------------------------------------------------- operator
 
 // Cells per tile along (x0, x1, x2).  2D: a task is one cell of one row (stage x0) or of one
-// column (stage x1), so a tile of C0 x C1 cells has (K (C1 + 1) + 1) C0 and K C0 C1 tasks; the
-// shapes keep K C0 near 64 output columns and both task counts near or above the workgroup size.
+// column (stage x1), so a tile of C0 x C1 cells has (K (C1 + 1) + 1) C0 and K C0 C1 tasks.  For
+// degrees 2-7 C0 makes the x0 stage one round of the 256-thread workgroup (232-252 tasks); two
+// rounds, with tiles of about 64 output columns, measured 20-28% slower at degrees 3-7 (FP64 apply,
+// 2D levels of 4-13M nodes).  Degree 1 keeps 64-cell rows (narrower tiles measured slower).
 template <int D, int K>
 struct OpShape {
-  static constexpr int C0 = D == 2 ? (K == 1 ? 64 : K == 2 ? 32 : K <= 4 ? 16 : K == 5 ? 12 : K == 6 ? 10 : 8)
-                                   : (16 / K > 1 ? 16 / K : 1);
+  static constexpr int C0 = D == 2 ? (K == 1 ? 64 : K == 2 ? 13 : K == 3 ? 9 : K <= 6 ? 8 : 7) : (16 / K > 1 ? 16 / K : 1);
   static constexpr int C1 = D == 2 ? (K == 1 ? 16 : K <= 3 ? 8 : K == 4 ? 6 : K == 5 ? 5 : 4)
                                    : (K == 1 ? 8 : K <= 4 ? 2 : 1);
   static constexpr int C2 = D == 3 ? C1 : 1;

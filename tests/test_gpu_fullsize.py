@@ -138,8 +138,8 @@ def test_colour_pass_every_patch(d, k, L, prec):
 
 # ------------------------------------------------------------------ operator and residual
 
-# 2D tiles hold (64, 32, 16, 16, 12, 10, 8) x (16, 8, 8, 6, 5, 4, 4) cells for K = 1..7: the 2D levels
-# below give 2..8 tiles per axis, ragged along x1 for K = 4, 5 and along x0 for K = 5, 6.
+# 2D tiles hold (64, 13, 9, 8, 8, 8, 7) x (16, 8, 8, 6, 5, 4, 4) cells for K = 1..7: the 2D levels
+# below give 2..8 tiles per axis, ragged along x0 for K = 2, 3, 7 and along x1 for K = 4, 5.
 OP_CASES = [(3, 1, 5), (3, 2, 5), (3, 3, 5), (3, 4, 5), (3, 5, 5), (3, 6, 5), (3, 7, 5), (3, 4, 6), (2, 7, 9),
             (2, 1, 7), (2, 2, 6), (2, 3, 6), (2, 4, 5), (2, 5, 5), (2, 6, 5), (2, 7, 5)]
 
