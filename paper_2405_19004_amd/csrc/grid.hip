@@ -900,11 +900,12 @@ __global__ __launch_bounds__(256) void restrict_plane_kernel(const T* __restrict
 // reduces along x0 (cell runs, restrict_run) and then along x1, and writes its coarse nodes, 0 on
 // the coarse boundary.  The tiles cover every coarse node; a non-null xz (the coarse iterate) is
 // zeroed on the same nodes.
-// Coarse cells per tile side: degree 7 takes 3 so that the x0 stage (IX CX tasks) is one round of
-// the workgroup (168 tasks; 4 cells gave 280: V-cycle of 2D Q7 512^2 812 -> 800 us with 3).
+// Coarse cells per tile side, chosen so that the x0 stage (IX CX tasks: 220, 224, 252, 240, 200,
+// 240, 168 for degrees 1-7) is one round of the workgroup.  Tiles of about 28 coarse nodes per
+// side took up to 6 rounds: 2D V-cycles 1-5% slower at degrees 1-4 and 7, equal at 5.
 template <int K, typename T>
 struct Res2D {
-  static constexpr int CX = K == 1 ? 28 : K == 2 ? 14 : K == 3 ? 9 : K == 4 ? 7 : K == 5 ? 5 : K == 6 ? 4 : 3;
+  static constexpr int CX = K == 1 ? 10 : K == 2 ? 7 : K == 3 ? 6 : K == 4 ? 5 : K <= 6 ? 4 : 3;
   static constexpr int TX = K * CX;          // coarse nodes per tile side
   static constexpr int NT = 256;
   static constexpr int IX = 2 * TX + 2 * K;  // fine extent per side
