@@ -508,12 +508,16 @@ __global__ __launch_bounds__((OpStream<K>::NT)) void op_stream_kernel(const T* _
 
 // Coarse cells per tile and threads: 3D cubic tiles (degree 1 only; the other degrees take the
 // tiles of prolong3_kernel below) span 2kC ~ 16 fine nodes per axis, so the last stage (one thread
-// per fine column) fills a 256-thread workgroup.  2D: a task is one coarse cell
-// of one row (stage x0) or of one fine column (stage x1), tiles span 2kC ~ 64 fine nodes.
+// per fine column) fills a 256-thread workgroup.  2D: a task is one coarse cell of one row (stage
+// x0) or of one fine column (stage x1); a tile of C0 x C1 coarse cells (about 64 fine columns by
+// 8k fine rows) makes both stages one round of the workgroup: (k C1 + 1) C0 and 2k C0 C1 tasks,
+// at most 256.  Square tiles took up to 8 rounds at degrees 1-4: 2D V-cycles 6% (degrees 1, 2),
+// 2-3% (3, 4) slower, equal at 5-7.
 template <int D, int K>
 struct ProShape {
-  static constexpr int C = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K <= 4 ? 8 : 4)
-                                  : (K == 1 ? 8 : K == 2 ? 4 : K <= 4 ? 2 : 1);
+  static constexpr int C = D == 2 ? 4 : (K == 1 ? 8 : K == 2 ? 4 : K <= 4 ? 2 : 1);  // 3D: cubic tiles
+  static constexpr int C0 = D == 2 ? (K == 1 ? 32 : K == 2 ? 16 : K == 3 ? 10 : K == 4 ? 8 : K == 5 ? 6 : K == 6 ? 5 : 4) : C;
+  static constexpr int C1 = D == 2 ? 4 : C;
   static constexpr int NT = D == 2 || K <= 4 ? 256 : 128;
 };
 
@@ -521,22 +525,24 @@ struct ProShape {
 // [2kC t, 2kC (t+1)), coarse inputs [kC t, kC (t+1)].
 template <int D, int K, typename T>
 __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(const T* __restrict__ e, T* __restrict__ xf,
-                                                                          long long n1dc, long long n1df, int tiles) {
-  constexpr int C = ProShape<D, K>::C, NT = ProShape<D, K>::NT;
+                                                                          long long n1dc, long long n1df, int tiles0,
+                                                                          int tiles1) {
+  constexpr int C = ProShape<D, K>::C, C0 = ProShape<D, K>::C0, C1 = ProShape<D, K>::C1, NT = ProShape<D, K>::NT;
   constexpr int TI = K * C + 1, TO = 2 * K * C, TIz = D == 3 ? TI : 1;
+  constexpr int TI1 = K * C1 + 1, TO0 = 2 * K * C0;  // 2D tile: coarse rows, fine columns
   constexpr int NP = K + 1;
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = blk % tiles, ty = (blk / tiles) % tiles, tz = D == 3 ? blk / (tiles * tiles) : 0;
-  const long long c0 = (long long)tx * K * C, c1 = (long long)ty * K * C, c2 = (long long)tz * K * C;
+  const int tx = blk % tiles0, ty = (blk / tiles0) % tiles1, tz = D == 3 ? blk / (tiles0 * tiles1) : 0;
+  const long long c0 = (long long)tx * K * C0, c1 = (long long)ty * K * C1, c2 = (long long)tz * K * C;
   const long long f0 = 2 * c0, f1 = 2 * c1, f2 = 2 * c2;
   const int tid = threadIdx.x;
   const long long nc2 = n1dc * n1dc, nf2 = n1df * n1df;
-  __shared__ T T1[TIz * TI * TO];
+  __shared__ T T1[D == 2 ? TI1 * TO0 : TIz * TI * TO];
   if constexpr (D == 2) {
     // stage x0: coarse cells cc of coarse rows yl
-    for (int task = tid; task < TI * C; task += NT) {
+    for (int task = tid; task < TI1 * C0; task += NT) {
       using CT = gen::CellTables<T, K>;
-      const int yl = task / C, cc = task - yl * C;
+      const int yl = task / C0, cc = task - yl * C0;
       const long long gy = c1 + yl;
       const bool ok = gy < n1dc && !is_bnd(gy, n1dc);
       const long long row = min(gy, n1dc - 1) * n1dc;
@@ -556,18 +562,18 @@ __global__ __launch_bounds__((ProShape<D, K>::NT)) void prolong_tile_kernel(cons
           if (q == 0 && a > 0) continue;
           s = fma_tab(CT::P[q * NP + a], in[a], s);
         }
-        T1[yl * TO + 2 * K * cc + q] = s;
+        T1[yl * TO0 + 2 * K * cc + q] = s;
       }
     }
     __syncthreads();
     // stage x1: coarse cells cc of fine columns xo; the thread's outputs are its own, every old value
     // is loaded before the first store
-    for (int task = tid; task < TO * C; task += NT) {
+    for (int task = tid; task < TO0 * C1; task += NT) {
       using CT = gen::CellTables<T, K>;
-      const int cc = task / TO, xo = task - cc * TO;
+      const int cc = task / TO0, xo = task - cc * TO0;
       T in[NP];
 #pragma unroll
-      for (int a = 0; a < NP; ++a) in[a] = T1[(K * cc + a) * TO + xo];
+      for (int a = 0; a < NP; ++a) in[a] = T1[(K * cc + a) * TO0 + xo];
       const long long gx = f0 + xo;
       T old[2 * K];
 #pragma unroll
@@ -1265,8 +1271,8 @@ bool pro_fits(const LevelGeom& fine) {
     return t0 * t1 <= 0x7fffffffLL && t0 * t1 * t2 <= 0x7fffffffLL;
   }
   using S = ProShape<D, K>;
-  const long long tiles = ceil_div(ncc, S::C);
-  return tiles <= 0x7fffffffLL && tiles * tiles * (D == 3 ? tiles : 1) <= 0x7fffffffLL;
+  const long long t0 = ceil_div(ncc, S::C0), t1 = ceil_div(ncc, S::C1);
+  return t0 * t1 <= 0x7fffffffLL && t0 * t1 * (D == 3 ? t0 : 1) <= 0x7fffffffLL;
 }
 
 template <int D, int K, typename T>
@@ -1283,10 +1289,10 @@ hipError_t pro_launch(const LevelGeom& fine, const void* e, void* xf, hipStream_
     return hipGetLastError();
   }
   using S = ProShape<D, K>;
-  const int tiles = ceil_div(ncc, S::C);
-  const long long blocks = (long long)tiles * tiles * (D == 3 ? tiles : 1);
+  const int t0 = ceil_div(ncc, S::C0), t1 = ceil_div(ncc, S::C1);
+  const long long blocks = (long long)t0 * t1 * (D == 3 ? t0 : 1);
   hipLaunchKernelGGL((prolong_tile_kernel<D, K, T>), dim3((unsigned)blocks), dim3(S::NT), 0, st, (const T*)e, (T*)xf,
-                     n1dc, fine.n1d, tiles);
+                     n1dc, fine.n1d, t0, t1);
   return hipGetLastError();
 }
 
